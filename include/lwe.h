@@ -1,0 +1,160 @@
+/*
+ * lwe.h -- C ABI of the MI355X plain-LWE KEM library (liblwe_hip.so).
+ *
+ * The scheme is the plain-LWE key encapsulation mechanism of Liberati et al.,
+ * "GPU Acceleration of Learning With Errors KEMs Using OpenACC for Post-Quantum
+ * Cryptography": the LWE relation b = A s + e mod q (Sec. 2.1, eq. (1)), the PKE
+ * algorithms KeyGen / Encrypt / Decrypt (Alg. 1-3) and the KEM Encaps / Decaps built on
+ * them with the Fujisaki-Okamoto transform and implicit rejection (Alg. 4-5, Sec. 2.1).
+ * It is used here in matrix form with nbar = mbar = 8 and q = 2^logq:
+ *
+ *   KeyGen (Alg. 1)  A = AES-128-CTR(seedA) (n x n, never stored; regenerated on demand
+ *                    as in Sec. 3.5), S^T, E^T from a 16-bit CDF table (seedSK),
+ *                    B^T = S^T A^T + E^T mod q
+ *   Encrypt (Alg. 2) S', E', E'' from the CDF table (coins),
+ *                    B' = S' A + E' mod q,  V = S' B + E'' + encode(mu) mod q
+ *   Decrypt (Alg. 3) M = V - B' S mod q,  mu = decode(M)
+ *   Encaps (Alg. 4)  coins = H(0x01 || H(pk) || mu)[0:16], K' = H(H(pk) || mu),
+ *                    ct = Encrypt(pk, mu; coins), K = H(K' || H(ct))
+ *   Decaps (Alg. 5)  mu' = Decrypt(sk, ct), re-encrypt, K = H(K'' || H(ct)) if the
+ *                    ciphertexts agree else H(z || H(ct)), in constant time.
+ *   H = SHA3-256.
+ *
+ * Byte formats (all integers little-endian, no bit packing):
+ *   pk = seedA[16] || B^T (8 x n uint16)
+ *   sk = S^T (8 x n int16) || pk || H(pk)[32] || z[32]
+ *   ct = B' (8 x n uint16, row major) || V (8 x 8 uint16)
+ *   mu = 64*B bits (B bits per coefficient), ss = 32 bytes.
+ *
+ * Conventions for every entry point:
+ *   - Buffers may be host or device memory (detected per pointer); device buffers must be
+ *     on the context's device.  All buffers are owned by the caller; the library keeps no
+ *     reference after the call returns.
+ *   - hip_stream == NULL runs the call synchronously on the context's own stream.  Otherwise
+ *     device work is queued on that stream (a hipStream_t).  Calls whose outputs include
+ *     host memory, and calls that hash on the host, synchronise the stream before returning;
+ *     device outputs are valid once the stream has been synchronised.
+ *   - The return value is an lwe_status.  On error, outputs are unspecified.
+ *   - A context is not thread-safe: use one context per host thread.
+ *   - Decaps of a malformed or tampered ciphertext is NOT an error: it returns LWE_OK and
+ *     the implicit-rejection key H(z || H(ct)).
+ */
+#ifndef LWE_H
+#define LWE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lwe_ctx lwe_ctx;
+
+typedef enum {
+  LWE_OK = 0,
+  LWE_EINVAL = -1,       /* bad argument: unknown parameter id, NULL pointer, bad size */
+  LWE_ENOMEM = -2,       /* device allocation failed or would exceed the context budget */
+  LWE_EDEVICE = -3,      /* a HIP runtime call failed */
+  LWE_EUNSUPPORTED = -4  /* valid request that this build does not implement */
+} lwe_status;
+
+/* Parameter set description (Table 1 of the paper gives the prime-q sets it evaluated;
+ * the sets registered here use q = 2^logq and a CDF-table error distribution). */
+typedef struct {
+  uint32_t n;      /* lattice dimension (multiple of 8) */
+  uint32_t logq;   /* q = 2^logq, 2 < logq <= 16 */
+  uint32_t B;      /* message bits per coefficient (64*B-bit messages) */
+  uint32_t K;      /* error support [-K, K] */
+  double sigma;    /* width of the discrete Gaussian the 16-bit CDF table approximates */
+  size_t pk_bytes, sk_bytes, ct_bytes, mu_bytes;
+} lwe_param_info;
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the device working
+ * memory the context may hold (0 = no limit); requests that need more fail with
+ * LWE_ENOMEM.  Returns LWE_EDEVICE if the device cannot be used. */
+int lwe_ctx_create(lwe_ctx** out, int device, size_t hbm_budget_bytes);
+void lwe_ctx_destroy(lwe_ctx* ctx);
+/* Device working memory currently held by the context, in bytes. */
+size_t lwe_ctx_device_bytes(const lwe_ctx* ctx);
+const char* lwe_strerror(int status);
+
+/* Parameter registry: id of the set for lattice dimension n, or a negative lwe_status. */
+int lwe_param_id(uint32_t n);
+/* Registers an additional parameter set (for experiments and tests; not security-vetted).
+ * Requires n % 8 == 0, 8 <= n <= 32768, 3 <= logq <= 16, 1 <= B <= 8 with B < logq,
+ * 1 <= K <= 15, sigma > 0, and a strictly increasing CDF table.  Returns the new id,
+ * or the id of an identical existing set, or a negative lwe_status. */
+int lwe_param_register(uint32_t n, uint32_t logq, uint32_t B, uint32_t K, double sigma);
+int lwe_param_get(int pid, lwe_param_info* out);
+size_t lwe_pk_bytes(int pid);
+size_t lwe_sk_bytes(int pid);
+size_t lwe_ct_bytes(int pid);
+size_t lwe_mu_bytes(int pid); /* shared secrets are always 32 bytes */
+/* The 16-bit CDF table of set pid: T[0..K] (K+1 entries) copied to host memory. */
+int lwe_cdf_table(int pid, uint16_t* T_out, size_t capacity);
+
+/* ---- KEM, derandomised: outputs are deterministic functions of the inputs ---- */
+
+/* KeyGen (Alg. 1) with explicit seeds.  seedA[16], seedSK[16], z[32]; pk/sk sized per pid. */
+int lwe_keygen(lwe_ctx* ctx, int pid, const uint8_t* seedA, const uint8_t* seedSK,
+               const uint8_t* z, uint8_t* pk, uint8_t* sk, void* hip_stream);
+/* Encaps (Alg. 4) with explicit message mu (lwe_mu_bytes(pid) bytes). */
+int lwe_encaps(lwe_ctx* ctx, int pid, const uint8_t* pk, const uint8_t* mu, uint8_t* ct,
+               uint8_t* ss, void* hip_stream);
+/* Decaps (Alg. 5), constant time with implicit rejection. */
+int lwe_decaps(lwe_ctx* ctx, int pid, const uint8_t* sk, const uint8_t* ct, uint8_t* ss,
+               void* hip_stream);
+
+/* ---- batched variants: `count` independent instances, arrays are [count][bytes] ----
+ * Each instance's output is identical to what the single-instance call returns for the
+ * same inputs.  encaps/decaps batches share one pk / one sk; keygen batches take count
+ * seed triples.  1 <= count <= 65535 (count == 0 is a no-op returning LWE_OK). */
+int lwe_keygen_batch(lwe_ctx* ctx, int pid, size_t count, const uint8_t* seedA,
+                     const uint8_t* seedSK, const uint8_t* z, uint8_t* pk, uint8_t* sk,
+                     void* hip_stream);
+int lwe_encaps_batch(lwe_ctx* ctx, int pid, size_t count, const uint8_t* pk, const uint8_t* mu,
+                     uint8_t* ct, uint8_t* ss, void* hip_stream);
+int lwe_decaps_batch(lwe_ctx* ctx, int pid, size_t count, const uint8_t* sk, const uint8_t* ct,
+                     uint8_t* ss, void* hip_stream);
+
+/* ---- test hooks (stable names, unstable semantics; for parity tests only) ---- */
+
+/* Columns col0 .. col0+ncols-1 of A for seedA: out[c*n + i] = A[i][col0 + c] (uint16),
+ * generated by the same device code the products use (Alg. 1, sample(rho)). */
+int lwe_test_expand_A(lwe_ctx* ctx, int pid, const uint8_t* seedA, uint32_t col0,
+                      uint32_t ncols, uint16_t* out, void* hip_stream);
+/* Raw AES-128-CTR keystream: nblocks 16-byte blocks of domain `domain` from block0. */
+int lwe_test_keystream(lwe_ctx* ctx, const uint8_t* key, uint32_t domain, uint64_t block0,
+                       size_t nblocks, uint8_t* out, void* hip_stream);
+/* count samples of the CDF sampler of set pid from keystream words word0.. of (key, domain),
+ * as int16. */
+int lwe_test_sample(lwe_ctx* ctx, int pid, const uint8_t* key, uint32_t domain, uint64_t word0,
+                    size_t count, int16_t* out, void* hip_stream);
+/* PKE encryption with explicit coins (no hashing): ct = Encrypt(pk, mu; coins). */
+int lwe_test_encrypt(lwe_ctx* ctx, int pid, size_t count, const uint8_t* pk,
+                     const uint8_t* coins /* [count][16] */, const uint8_t* mu, uint8_t* ct,
+                     void* hip_stream);
+/* PKE decryption without re-encryption: mu = Decrypt(sk, ct) for count ciphertexts. */
+int lwe_test_decrypt(lwe_ctx* ctx, int pid, size_t count, const uint8_t* sk, const uint8_t* ct,
+                     uint8_t* mu, void* hip_stream);
+/* SHA3-256 of count messages of len bytes each ([count][len] -> [count][32]), computed
+ * by the device sponge. */
+int lwe_test_sha3(lwe_ctx* ctx, size_t count, size_t len, const uint8_t* in, uint8_t* out,
+                  void* hip_stream);
+
+/* Tuning knobs of the batched product kernel (see lwe_tune_* in the Python package).
+ * Zero leaves a knob at its built-in default. */
+typedef struct {
+  uint32_t col_groups;   /* 16-column groups per workgroup strip (1, 2 or 4) */
+  uint32_t row_groups;   /* 16-row groups per wave in the streaming loop (1, 2 or 4) */
+  uint32_t m_chunks;     /* row chunks sharing one regenerated strip of A */
+  uint32_t host_hash_max;/* batches up to this size hash on the host */
+} lwe_tuning;
+int lwe_set_tuning(lwe_ctx* ctx, int pid, const lwe_tuning* t);
+int lwe_get_tuning(lwe_ctx* ctx, int pid, lwe_tuning* t);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LWE_H */

@@ -1,0 +1,860 @@
+// Host side of liblwe_hip: contexts, device working memory, staging of host buffers,
+// launch planning and the C ABI entry points declared in include/lwe.h.
+#include <string.h>
+
+#include <algorithm>
+#include <thread>
+#include <vector>
+
+#include "lwe_internal.h"
+
+using namespace lwe;
+
+namespace {
+
+// batch sizes map to grid.y of the sampling and keygen kernels
+constexpr size_t LWE_MAX_BATCH = 65535;
+
+enum BufId {
+  B_SEEDA, B_SEEDSK, B_Z, B_RKA, B_RK, B_X, B_E, B_E2, B_COINS, B_KP, B_HCT, B_FLAGS, B_MU2,
+  B_ACC, B_PK, B_SK, B_CT, B_MU, B_SS, B_PKH, B_TEST, B_COUNT
+};
+
+struct Buf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+}  // namespace
+
+struct lwe_ctx {
+  int device = 0;
+  hipStream_t own = nullptr;
+  size_t budget = 0;  // 0 = unlimited
+  size_t held = 0;
+  uint32_t* d_T0 = nullptr;
+  Buf bufs[B_COUNT];
+  // cache of the last public key hashed on the host
+  std::vector<uint8_t> pk_cache;
+  uint8_t pkh_cache[32];
+  lwe_tuning tuning[256];
+  int host_threads = 1;
+};
+
+namespace {
+
+struct DevGuard {
+  int prev = -1;
+  explicit DevGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DevGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+#define HIP_CHECK(x)                          \
+  do {                                        \
+    hipError_t e_ = (x);                      \
+    if (e_ != hipSuccess) return LWE_EDEVICE; \
+  } while (0)
+
+#define LWE_CHECK(x)          \
+  do {                        \
+    int s_ = (x);             \
+    if (s_ != LWE_OK) return s_; \
+  } while (0)
+
+bool is_device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t attr;
+  hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice || attr.isManaged;
+}
+
+// Returns a device buffer of at least `bytes`, growing it when needed.
+int ensure(lwe_ctx* c, BufId id, size_t bytes, void** out) {
+  Buf& b = c->bufs[id];
+  if (bytes == 0) bytes = 16;
+  if (b.cap < bytes) {
+    size_t want = std::max(bytes, b.cap + b.cap / 2);
+    want = (want + 255) & ~(size_t)255;
+    if (c->budget && c->held - b.cap + want > c->budget) {
+      want = (bytes + 255) & ~(size_t)255;
+      if (c->held - b.cap + want > c->budget) return LWE_ENOMEM;
+    }
+    if (b.p) {
+      // the old buffer may still be read by queued work
+      if (hipDeviceSynchronize() != hipSuccess) return LWE_EDEVICE;
+      (void)hipFree(b.p);
+      c->held -= b.cap;
+      b.p = nullptr;
+      b.cap = 0;
+    }
+    if (hipMalloc(&b.p, want) != hipSuccess) {
+      (void)hipGetLastError();
+      b.p = nullptr;
+      return LWE_ENOMEM;
+    }
+    b.cap = want;
+    c->held += want;
+  }
+  *out = b.p;
+  return LWE_OK;
+}
+
+template <class T>
+int ensure_t(lwe_ctx* c, BufId id, size_t bytes, T** out) {
+  void* p = nullptr;
+  int s = ensure(c, id, bytes, &p);
+  *out = (T*)p;
+  return s;
+}
+
+// Device view of a caller input: the pointer itself if it is device memory, otherwise a
+// copy in buffer `id`.
+int stage_in(lwe_ctx* c, BufId id, const void* src, size_t bytes, hipStream_t s, const uint8_t** dev) {
+  if (is_device_ptr(src)) {
+    *dev = (const uint8_t*)src;
+    return LWE_OK;
+  }
+  uint8_t* d = nullptr;
+  LWE_CHECK(ensure_t(c, id, bytes, &d));
+  HIP_CHECK(hipMemcpyAsync(d, src, bytes, hipMemcpyHostToDevice, s));
+  *dev = d;
+  return LWE_OK;
+}
+
+// Host copy of a caller buffer (which may be on the device); synchronises when copying.
+int host_copy(const void* src, size_t bytes, hipStream_t s, std::vector<uint8_t>& out) {
+  out.resize(bytes);
+  if (is_device_ptr(src)) {
+    HIP_CHECK(hipMemcpyAsync(out.data(), src, bytes, hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+  } else {
+    memcpy(out.data(), src, bytes);
+  }
+  return LWE_OK;
+}
+
+struct OutStage {
+  void* user = nullptr;
+  uint8_t* dev = nullptr;
+  size_t bytes = 0;
+  bool host = false;
+};
+
+int stage_out(lwe_ctx* c, BufId id, void* user, size_t bytes, OutStage& o) {
+  o.user = user;
+  o.bytes = bytes;
+  o.host = !is_device_ptr(user);
+  if (o.host) {
+    LWE_CHECK(ensure_t(c, id, bytes, &o.dev));
+  } else {
+    o.dev = (uint8_t*)user;
+  }
+  return LWE_OK;
+}
+
+int finish_out(const OutStage& o, hipStream_t s) {
+  if (o.host && o.bytes) HIP_CHECK(hipMemcpyAsync(o.user, o.dev, o.bytes, hipMemcpyDeviceToHost, s));
+  return LWE_OK;
+}
+
+hipStream_t pick_stream(lwe_ctx* c, void* user) { return user ? (hipStream_t)user : c->own; }
+
+// Parallel loop over [0, count) on host threads (used for host-side hashing).
+template <class F>
+void host_for(int threads, size_t count, F f) {
+  if (threads <= 1 || count < 4) {
+    for (size_t i = 0; i < count; ++i) f(i);
+    return;
+  }
+  const int nt = (int)std::min<size_t>((size_t)threads, count);
+  std::vector<std::thread> th;
+  th.reserve(nt);
+  for (int t = 0; t < nt; ++t)
+    th.emplace_back([=, &f]() {
+      for (size_t i = t; i < count; i += nt) f(i);
+    });
+  for (auto& x : th) x.join();
+}
+
+const lwe_tuning& tuning_of(lwe_ctx* c, int pid) { return c->tuning[pid & 255]; }
+
+bool use_host_hash(lwe_ctx* c, int pid, size_t count) {
+  const lwe_tuning& t = tuning_of(c, pid);
+  const size_t lim = t.host_hash_max ? t.host_hash_max : 16;
+  return count <= lim;
+}
+
+// ------------------------------------------------------------------------------------
+// Product launch planning
+// ------------------------------------------------------------------------------------
+int run_product(lwe_ctx* c, int pid, const Params& p, ProdArgs a, bool trans, hipStream_t s) {
+  // a: operands, epilogue fields, M and ncols are filled in by the caller
+  const int ksteps = (p.n + 63) / 64;
+  const lwe_tuning& tu = tuning_of(c, pid);
+  const bool strip = !trans && !a.per_inst_A && a.M >= 256;
+  if (!strip) {
+    int RG = 1;
+    if (!a.per_inst_A) RG = a.M <= 16 ? 1 : (a.M <= 32 ? 2 : 4);
+    const int CG = 1;
+    a.m_tile = a.per_inst_A ? 8 : 16 * RG;
+    a.n_mt = a.per_inst_A ? a.M / 8 : (a.M + a.m_tile - 1) / a.m_tile;
+    a.n_jt = (a.ncols + 16 * CG - 1) / (16 * CG);
+    const long long units = (long long)a.n_jt * a.n_mt * ksteps;
+    int KS = (int)std::max<long long>(1, (units + 65535) / 65536);
+    int W = std::min(16, (ksteps + KS - 1) / KS);
+    a.n_kc = (ksteps + W * KS - 1) / (W * KS);
+    W = (ksteps + a.n_kc * KS - 1) / (a.n_kc * KS);
+    a.kc_len = W * KS * 64;
+    if (a.n_kc > 1) {
+      a.acc_ld = a.ncols;
+      LWE_CHECK(ensure_t(c, B_ACC, (size_t)a.M * a.acc_ld * 4, &a.acc32));
+      HIP_CHECK(launch_fill_u32((uint32_t*)a.acc32, (size_t)a.M * a.acc_ld, 0, s));
+    }
+    HIP_CHECK(launch_product_stream(a, CG, RG, W, trans, a.n_mt, KS, s));
+  } else {
+    int CG = tu.col_groups ? (int)tu.col_groups : 2;
+    int RG = tu.row_groups ? (int)tu.row_groups : 4;
+    const int max_rows = (int)(((160 * 1024 - 4096) / (32 * CG)) / 64 * 64);
+    a.kc_len = std::min(ksteps * 64, max_rows);
+    a.n_kc = (p.n + a.kc_len - 1) / a.kc_len;
+    a.n_jt = (a.ncols + 16 * CG - 1) / (16 * CG);
+    int mch = tu.m_chunks ? (int)tu.m_chunks : std::max(1, (512 + a.n_jt * a.n_kc - 1) / (a.n_jt * a.n_kc) / 2);
+    const int unit = 16 * RG;
+    const int m_units = (a.M + unit - 1) / unit;
+    mch = std::min(mch, m_units);
+    a.m_tile = ((m_units + mch - 1) / mch) * unit;
+    a.n_mt = (a.M + a.m_tile - 1) / a.m_tile;
+    if (a.n_kc > 1) {
+      a.acc_ld = a.ncols;
+      LWE_CHECK(ensure_t(c, B_ACC, (size_t)a.M * a.acc_ld * 4, &a.acc32));
+      HIP_CHECK(launch_fill_u32((uint32_t*)a.acc32, (size_t)a.M * a.acc_ld, 0, s));
+    }
+    HIP_CHECK(launch_product_strip(a, CG, RG, s));
+  }
+  if (a.n_kc > 1) HIP_CHECK(launch_finalize(a, s));
+  return LWE_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// Core operations on device-resident data
+// ------------------------------------------------------------------------------------
+
+// Encrypt `count` messages under one public key with per-instance coins already expanded
+// into round keys at d_rk.  Writes ct records (or, in compare mode, sets flags).
+int encrypt_core(lwe_ctx* c, int pid, const Params& p, size_t count, const uint8_t* pk_dev,
+                 const uint32_t* d_rk, const uint8_t* mu_dev, size_t mu_stride, uint8_t* ct_out,
+                 const uint8_t* ct_cmp, uint32_t* flags, hipStream_t s) {
+  const int n = p.n;
+  int8_t *X, *E, *E2;
+  uint32_t* rkA;
+  LWE_CHECK(ensure_t(c, B_X, count * 8 * (size_t)p.ldx, &X));
+  LWE_CHECK(ensure_t(c, B_E, count * 8 * (size_t)n, &E));
+  LWE_CHECK(ensure_t(c, B_E2, count * 64, &E2));
+  LWE_CHECK(ensure_t(c, B_RKA, 44 * 4, &rkA));
+  HIP_CHECK(launch_expand_keys(pk_dev, 0, 1, c->d_T0, rkA, s));
+  SampleArgs sa;
+  memset(&sa, 0, sizeof(sa));
+  sa.rk = d_rk;
+  sa.T0 = c->d_T0;
+  sa.n = n;
+  sa.K = p.K;
+  sa.ldx = p.ldx;
+  sa.nseg = 3;
+  for (int k = 0; k <= MAX_K; ++k) sa.T[k] = p.T[k];
+  sa.X = X;
+  sa.E = E;
+  sa.E2 = E2;
+  sa.chunk = 2048;
+  HIP_CHECK(launch_sample(sa, (int)count, s));
+  ProdArgs a;
+  memset(&a, 0, sizeof(a));
+  a.rkA = rkA;
+  a.T0 = c->d_T0;
+  a.X = X;
+  a.ldx = p.ldx;
+  a.M = (int)(count * 8);
+  a.n = n;
+  a.logq = p.logq;
+  a.B = p.B;
+  a.ncols = n + 8;
+  a.Bt = pk_dev + 16;
+  a.mode = ct_cmp ? PM_COMPARE : PM_ENCRYPT;
+  a.E = E;
+  a.E2 = E2;
+  a.mu = mu_dev;
+  a.mu_stride = mu_stride;
+  a.out = ct_out;
+  a.out_stride = p.ct_bytes;
+  a.out_off = 0;
+  a.cmp = ct_cmp;
+  a.cmp_stride = p.ct_bytes;
+  a.flags = flags;
+  return run_product(c, pid, p, a, false, s);
+}
+
+int check_pid(int pid, const Params** pp) {
+  const Params* p = get_params(pid);
+  if (!p) return LWE_EINVAL;
+  *pp = p;
+  return LWE_OK;
+}
+
+void host_pkh(lwe_ctx* c, const uint8_t* pk, size_t len, uint8_t out[32]) {
+  if (c->pk_cache.size() == len && memcmp(c->pk_cache.data(), pk, len) == 0) {
+    memcpy(out, c->pkh_cache, 32);
+    return;
+  }
+  sha3_256(pk, len, out);
+  c->pk_cache.assign(pk, pk + len);
+  memcpy(c->pkh_cache, out, 32);
+}
+
+}  // namespace
+
+// =====================================================================================
+// C ABI
+// =====================================================================================
+extern "C" {
+
+const char* lwe_strerror(int status) {
+  switch (status) {
+    case LWE_OK: return "ok";
+    case LWE_EINVAL: return "invalid argument";
+    case LWE_ENOMEM: return "out of device memory or over the context budget";
+    case LWE_EDEVICE: return "HIP runtime error";
+    case LWE_EUNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+int lwe_ctx_create(lwe_ctx** out, int device, size_t hbm_budget_bytes) {
+  if (!out) return LWE_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    (void)hipGetLastError();
+    return LWE_EDEVICE;
+  }
+  DevGuard g(device);
+  lwe_ctx* c = new lwe_ctx();
+  c->device = device;
+  c->budget = hbm_budget_bytes;
+  memset(c->tuning, 0, sizeof(c->tuning));
+  unsigned hc = std::thread::hardware_concurrency();
+  c->host_threads = (int)std::max(1u, std::min(hc, 16u));
+  if (hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess ||
+      hipMalloc(&c->d_T0, 1024) != hipSuccess ||
+      hipMemcpy(c->d_T0, aes_T0(), 1024, hipMemcpyHostToDevice) != hipSuccess ||
+      init_kernels() != hipSuccess) {
+    (void)hipGetLastError();
+    lwe_ctx_destroy(c);
+    return LWE_EDEVICE;
+  }
+  *out = c;
+  return LWE_OK;
+}
+
+void lwe_ctx_destroy(lwe_ctx* c) {
+  if (!c) return;
+  DevGuard g(c->device);
+  (void)hipDeviceSynchronize();
+  for (auto& b : c->bufs)
+    if (b.p) (void)hipFree(b.p);
+  if (c->d_T0) (void)hipFree(c->d_T0);
+  if (c->own) (void)hipStreamDestroy(c->own);
+  delete c;
+}
+
+size_t lwe_ctx_device_bytes(const lwe_ctx* c) { return c ? c->held + 1024 : 0; }
+
+int lwe_param_id(uint32_t n) { return find_param(n); }
+
+int lwe_param_register(uint32_t n, uint32_t logq, uint32_t B, uint32_t K, double sigma) {
+  return register_param(n, logq, B, K, sigma);
+}
+
+int lwe_param_get(int pid, lwe_param_info* out) {
+  const Params* p = get_params(pid);
+  if (!p || !out) return LWE_EINVAL;
+  out->n = (uint32_t)p->n;
+  out->logq = (uint32_t)p->logq;
+  out->B = (uint32_t)p->B;
+  out->K = (uint32_t)p->K;
+  out->sigma = p->sigma;
+  out->pk_bytes = p->pk_bytes;
+  out->sk_bytes = p->sk_bytes;
+  out->ct_bytes = p->ct_bytes;
+  out->mu_bytes = p->mu_bytes;
+  return LWE_OK;
+}
+
+size_t lwe_pk_bytes(int pid) {
+  const Params* p = get_params(pid);
+  return p ? p->pk_bytes : 0;
+}
+size_t lwe_sk_bytes(int pid) {
+  const Params* p = get_params(pid);
+  return p ? p->sk_bytes : 0;
+}
+size_t lwe_ct_bytes(int pid) {
+  const Params* p = get_params(pid);
+  return p ? p->ct_bytes : 0;
+}
+size_t lwe_mu_bytes(int pid) {
+  const Params* p = get_params(pid);
+  return p ? p->mu_bytes : 0;
+}
+
+int lwe_cdf_table(int pid, uint16_t* T_out, size_t capacity) {
+  const Params* p = get_params(pid);
+  if (!p || !T_out || capacity < (size_t)p->K + 1) return LWE_EINVAL;
+  for (int k = 0; k <= p->K; ++k) T_out[k] = p->T[k];
+  return LWE_OK;
+}
+
+int lwe_set_tuning(lwe_ctx* c, int pid, const lwe_tuning* t) {
+  if (!c || !t || !get_params(pid)) return LWE_EINVAL;
+  if (t->col_groups && t->col_groups != 1 && t->col_groups != 2 && t->col_groups != 4) return LWE_EINVAL;
+  if (t->row_groups && t->row_groups != 1 && t->row_groups != 2 && t->row_groups != 4) return LWE_EINVAL;
+  if (t->col_groups == 4 && t->row_groups == 4) return LWE_EINVAL;
+  c->tuning[pid & 255] = *t;
+  return LWE_OK;
+}
+
+int lwe_get_tuning(lwe_ctx* c, int pid, lwe_tuning* t) {
+  if (!c || !t || !get_params(pid)) return LWE_EINVAL;
+  *t = c->tuning[pid & 255];
+  return LWE_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// KeyGen (Alg. 1): B^T = S^T A^T + E^T; pk = seedA || B^T; sk = S^T || pk || H(pk) || z
+// ---------------------------------------------------------------------------------------
+int lwe_keygen_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* seedA, const uint8_t* seedSK,
+                     const uint8_t* z, uint8_t* pk, uint8_t* sk, void* stream) {
+  const Params* pp;
+  if (!c) return LWE_EINVAL;
+  LWE_CHECK(check_pid(pid, &pp));
+  if (count == 0) return LWE_OK;
+  if (!seedA || !seedSK || !z || !pk || !sk || count > LWE_MAX_BATCH) return LWE_EINVAL;
+  const Params& p = *pp;
+  DevGuard g(c->device);
+  hipStream_t s = pick_stream(c, stream);
+  const int n = p.n;
+  const uint8_t *dA, *dS, *dZ;
+  LWE_CHECK(stage_in(c, B_SEEDA, seedA, count * 16, s, &dA));
+  LWE_CHECK(stage_in(c, B_SEEDSK, seedSK, count * 16, s, &dS));
+  LWE_CHECK(stage_in(c, B_Z, z, count * 32, s, &dZ));
+  OutStage opk, osk;
+  LWE_CHECK(stage_out(c, B_PK, pk, count * p.pk_bytes, opk));
+  LWE_CHECK(stage_out(c, B_SK, sk, count * p.sk_bytes, osk));
+  uint32_t *rkA, *rkS;
+  int8_t *X, *E;
+  LWE_CHECK(ensure_t(c, B_RKA, count * 44 * 4, &rkA));
+  LWE_CHECK(ensure_t(c, B_RK, count * 44 * 4, &rkS));
+  LWE_CHECK(ensure_t(c, B_X, count * 8 * (size_t)p.ldx, &X));
+  LWE_CHECK(ensure_t(c, B_E, count * 8 * (size_t)n, &E));
+  HIP_CHECK(launch_expand_keys(dA, 16, (int)count, c->d_T0, rkA, s));
+  HIP_CHECK(launch_expand_keys(dS, 16, (int)count, c->d_T0, rkS, s));
+  SampleArgs sa;
+  memset(&sa, 0, sizeof(sa));
+  sa.rk = rkS;
+  sa.T0 = c->d_T0;
+  sa.n = n;
+  sa.K = p.K;
+  sa.ldx = p.ldx;
+  sa.nseg = 2;
+  for (int k = 0; k <= MAX_K; ++k) sa.T[k] = p.T[k];
+  sa.X = X;
+  sa.X16 = osk.dev;  // S^T int16 at the start of each sk record
+  sa.x16_stride = p.sk_bytes;
+  sa.E = E;
+  sa.chunk = 2048;
+  HIP_CHECK(launch_sample(sa, (int)count, s));
+  ProdArgs a;
+  memset(&a, 0, sizeof(a));
+  a.rkA = rkA;
+  a.T0 = c->d_T0;
+  a.X = X;
+  a.ldx = p.ldx;
+  a.M = (int)(count * 8);
+  a.n = n;
+  a.logq = p.logq;
+  a.B = p.B;
+  a.ncols = n;
+  a.per_inst_A = 1;
+  a.mode = PM_KEYGEN;
+  a.E = E;
+  a.out = opk.dev;
+  a.out_stride = p.pk_bytes;
+  a.out_off = 16;
+  LWE_CHECK(run_product(c, pid, p, a, true, s));
+  // pk = seedA || B^T ; sk = S^T || pk || H(pk) || z
+  HIP_CHECK(hipMemcpy2DAsync(opk.dev, p.pk_bytes, dA, 16, 16, count, hipMemcpyDeviceToDevice, s));
+  const size_t off_pk = (size_t)16 * n, off_pkh = off_pk + p.pk_bytes, off_z = off_pkh + 32;
+  HIP_CHECK(hipMemcpy2DAsync(osk.dev + off_pk, p.sk_bytes, opk.dev, p.pk_bytes, p.pk_bytes, count,
+                             hipMemcpyDeviceToDevice, s));
+  HIP_CHECK(hipMemcpy2DAsync(osk.dev + off_z, p.sk_bytes, dZ, 32, 32, count, hipMemcpyDeviceToDevice, s));
+  if (use_host_hash(c, pid, count)) {
+    std::vector<uint8_t> hpk(count * p.pk_bytes), hh(count * 32);
+    HIP_CHECK(hipMemcpyAsync(hpk.data(), opk.dev, hpk.size(), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    host_for(c->host_threads, count,
+             [&](size_t i) { sha3_256(hpk.data() + i * p.pk_bytes, p.pk_bytes, hh.data() + i * 32); });
+    uint8_t* dh;
+    LWE_CHECK(ensure_t(c, B_HCT, count * 32, &dh));
+    HIP_CHECK(hipMemcpyAsync(dh, hh.data(), hh.size(), hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipMemcpy2DAsync(osk.dev + off_pkh, p.sk_bytes, dh, 32, 32, count, hipMemcpyDeviceToDevice, s));
+    HIP_CHECK(hipStreamSynchronize(s));  // hh must outlive the copy
+  } else {
+    uint8_t* dh;
+    LWE_CHECK(ensure_t(c, B_HCT, count * 32, &dh));
+    HIP_CHECK(launch_hash_records((int)count, opk.dev, p.pk_bytes, p.pk_bytes, dh, s));
+    HIP_CHECK(hipMemcpy2DAsync(osk.dev + off_pkh, p.sk_bytes, dh, 32, 32, count, hipMemcpyDeviceToDevice, s));
+  }
+  LWE_CHECK(finish_out(opk, s));
+  LWE_CHECK(finish_out(osk, s));
+  if (opk.host || osk.host || !stream) HIP_CHECK(hipStreamSynchronize(s));
+  return LWE_OK;
+}
+
+int lwe_keygen(lwe_ctx* c, int pid, const uint8_t* seedA, const uint8_t* seedSK, const uint8_t* z,
+               uint8_t* pk, uint8_t* sk, void* stream) {
+  return lwe_keygen_batch(c, pid, 1, seedA, seedSK, z, pk, sk, stream);
+}
+
+// ---------------------------------------------------------------------------------------
+// Encaps (Alg. 4): coins = H(0x01 || H(pk) || mu)[0:16], K' = H(H(pk) || mu),
+// ct = Encrypt(pk, mu; coins), K = H(K' || H(ct))
+// ---------------------------------------------------------------------------------------
+int lwe_encaps_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* pk, const uint8_t* mu,
+                     uint8_t* ct, uint8_t* ss, void* stream) {
+  const Params* pp;
+  if (!c) return LWE_EINVAL;
+  LWE_CHECK(check_pid(pid, &pp));
+  if (count == 0) return LWE_OK;
+  if (!pk || !mu || !ct || !ss || count > LWE_MAX_BATCH) return LWE_EINVAL;
+  const Params& p = *pp;
+  DevGuard g(c->device);
+  hipStream_t s = pick_stream(c, stream);
+  const size_t mb = p.mu_bytes;
+  // H(pk) on the host (cached per public key)
+  std::vector<uint8_t> hpk;
+  LWE_CHECK(host_copy(pk, p.pk_bytes, s, hpk));
+  uint8_t pkh[32];
+  host_pkh(c, hpk.data(), p.pk_bytes, pkh);
+  const uint8_t *dpk, *dmu;
+  LWE_CHECK(stage_in(c, B_PK, pk, p.pk_bytes, s, &dpk));
+  LWE_CHECK(stage_in(c, B_MU, mu, count * mb, s, &dmu));
+  OutStage oct, oss;
+  LWE_CHECK(stage_out(c, B_CT, ct, count * p.ct_bytes, oct));
+  LWE_CHECK(stage_out(c, B_SS, ss, count * 32, oss));
+  uint8_t *dcoins, *dkp;
+  uint32_t* drk;
+  LWE_CHECK(ensure_t(c, B_COINS, count * 16, &dcoins));
+  LWE_CHECK(ensure_t(c, B_KP, count * 32, &dkp));
+  LWE_CHECK(ensure_t(c, B_RK, count * 44 * 4, &drk));
+  const bool hh = use_host_hash(c, pid, count);
+  std::vector<uint8_t> hmu, hcoins, hkp;
+  if (hh) {
+    LWE_CHECK(host_copy(mu, count * mb, s, hmu));
+    hcoins.resize(count * 16);
+    hkp.resize(count * 32);
+    const uint8_t one = 1;
+    host_for(c->host_threads, count, [&](size_t i) {
+      uint8_t h[32];
+      sha3_256_3(&one, 1, pkh, 32, hmu.data() + i * mb, mb, h);
+      memcpy(hcoins.data() + i * 16, h, 16);
+      sha3_256_3(pkh, 32, hmu.data() + i * mb, mb, nullptr, 0, hkp.data() + i * 32);
+    });
+    HIP_CHECK(hipMemcpyAsync(dcoins, hcoins.data(), count * 16, hipMemcpyHostToDevice, s));
+  } else {
+    uint8_t* dpkh;
+    LWE_CHECK(ensure_t(c, B_PKH, 32, &dpkh));
+    HIP_CHECK(hipMemcpyAsync(dpkh, pkh, 32, hipMemcpyHostToDevice, s));
+    HIP_CHECK(launch_fo_coins((int)count, dpkh, dmu, mb, (int)mb, dcoins, dkp, s));
+  }
+  HIP_CHECK(launch_expand_keys(dcoins, 16, (int)count, c->d_T0, drk, s));
+  LWE_CHECK(encrypt_core(c, pid, p, count, dpk, drk, dmu, mb, oct.dev, nullptr, nullptr, s));
+  if (hh) {
+    std::vector<uint8_t> hct(count * p.ct_bytes), hss(count * 32);
+    HIP_CHECK(hipMemcpyAsync(hct.data(), oct.dev, hct.size(), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    host_for(c->host_threads, count, [&](size_t i) {
+      uint8_t h[32];
+      sha3_256(hct.data() + i * p.ct_bytes, p.ct_bytes, h);
+      sha3_256_3(hkp.data() + i * 32, 32, h, 32, nullptr, 0, hss.data() + i * 32);
+    });
+    if (oss.host) {
+      memcpy(ss, hss.data(), hss.size());
+      oss.bytes = 0;
+    } else {
+      HIP_CHECK(hipMemcpyAsync(oss.dev, hss.data(), hss.size(), hipMemcpyHostToDevice, s));
+      HIP_CHECK(hipStreamSynchronize(s));
+    }
+  } else {
+    uint8_t* dhct;
+    LWE_CHECK(ensure_t(c, B_HCT, count * 32, &dhct));
+    HIP_CHECK(launch_hash_records((int)count, oct.dev, p.ct_bytes, p.ct_bytes, dhct, s));
+    HIP_CHECK(launch_final_ss((int)count, nullptr, dkp, nullptr, dhct, oss.dev, s));
+  }
+  LWE_CHECK(finish_out(oct, s));
+  LWE_CHECK(finish_out(oss, s));
+  if (oct.host || oss.host || !stream) HIP_CHECK(hipStreamSynchronize(s));
+  return LWE_OK;
+}
+
+int lwe_encaps(lwe_ctx* c, int pid, const uint8_t* pk, const uint8_t* mu, uint8_t* ct, uint8_t* ss,
+               void* stream) {
+  return lwe_encaps_batch(c, pid, 1, pk, mu, ct, ss, stream);
+}
+
+// ---------------------------------------------------------------------------------------
+// Decaps (Alg. 5): mu' = Decrypt(sk, ct); coins', K'' from mu'; ct' = Encrypt(pk, mu'; coins');
+// K = H(K'' || H(ct)) if ct' == ct else H(z || H(ct)), selected in constant time.
+// ---------------------------------------------------------------------------------------
+int lwe_decaps_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* sk, const uint8_t* ct,
+                     uint8_t* ss, void* stream) {
+  const Params* pp;
+  if (!c) return LWE_EINVAL;
+  LWE_CHECK(check_pid(pid, &pp));
+  if (count == 0) return LWE_OK;
+  if (!sk || !ct || !ss || count > LWE_MAX_BATCH) return LWE_EINVAL;
+  const Params& p = *pp;
+  DevGuard g(c->device);
+  hipStream_t s = pick_stream(c, stream);
+  const int n = p.n;
+  const size_t mb = p.mu_bytes;
+  const size_t off_pk = (size_t)16 * n, off_pkh = off_pk + p.pk_bytes, off_z = off_pkh + 32;
+  const uint8_t *dsk, *dct;
+  LWE_CHECK(stage_in(c, B_SK, sk, p.sk_bytes, s, &dsk));
+  LWE_CHECK(stage_in(c, B_CT, ct, count * p.ct_bytes, s, &dct));
+  OutStage oss;
+  LWE_CHECK(stage_out(c, B_SS, ss, count * 32, oss));
+  uint8_t *dmu2, *dcoins, *dkp;
+  uint32_t *drk, *dflags;
+  LWE_CHECK(ensure_t(c, B_MU2, count * mb, &dmu2));
+  LWE_CHECK(ensure_t(c, B_COINS, count * 16, &dcoins));
+  LWE_CHECK(ensure_t(c, B_KP, count * 32, &dkp));
+  LWE_CHECK(ensure_t(c, B_RK, count * 44 * 4, &drk));
+  LWE_CHECK(ensure_t(c, B_FLAGS, count * 4, &dflags));
+  // mu' = Decrypt(sk, ct)
+  DecArgs da;
+  da.ct = dct;
+  da.ct_stride = p.ct_bytes;
+  da.St16 = dsk;
+  da.n = n;
+  da.logq = p.logq;
+  da.B = p.B;
+  da.count = (int)count;
+  da.mu_bytes = (int)mb;
+  da.mu_out = dmu2;
+  HIP_CHECK(launch_decrypt(da, s));
+  const bool hh = use_host_hash(c, pid, count);
+  std::vector<uint8_t> hsk_tail, hkp, hct, hhct;
+  if (hh) {
+    // pkh and z from the secret key, mu' to the host, coins' and K'' on the host
+    std::vector<uint8_t> hmu(count * mb), hcoins(count * 16);
+    hsk_tail.resize(64);
+    HIP_CHECK(hipMemcpyAsync(hsk_tail.data(), dsk + off_pkh, 64, hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipMemcpyAsync(hmu.data(), dmu2, hmu.size(), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    hkp.resize(count * 32);
+    const uint8_t one = 1;
+    const uint8_t* pkh = hsk_tail.data();
+    host_for(c->host_threads, count, [&](size_t i) {
+      uint8_t h[32];
+      sha3_256_3(&one, 1, pkh, 32, hmu.data() + i * mb, mb, h);
+      memcpy(hcoins.data() + i * 16, h, 16);
+      sha3_256_3(pkh, 32, hmu.data() + i * mb, mb, nullptr, 0, hkp.data() + i * 32);
+    });
+    HIP_CHECK(hipMemcpyAsync(dcoins, hcoins.data(), count * 16, hipMemcpyHostToDevice, s));
+    HIP_CHECK(launch_expand_keys(dcoins, 16, (int)count, c->d_T0, drk, s));
+    HIP_CHECK(launch_fill_u32(dflags, count, 0, s));
+    LWE_CHECK(encrypt_core(c, pid, p, count, dsk + off_pk, drk, dmu2, mb, nullptr, dct, dflags, s));
+    std::vector<uint32_t> hflags(count);
+    HIP_CHECK(hipMemcpyAsync(hflags.data(), dflags, count * 4, hipMemcpyDeviceToHost, s));
+    // H(ct) on the host while the device re-encrypts
+    LWE_CHECK(host_copy(ct, count * p.ct_bytes, s, hct));
+    hhct.resize(count * 32);
+    host_for(c->host_threads, count,
+             [&](size_t i) { sha3_256(hct.data() + i * p.ct_bytes, p.ct_bytes, hhct.data() + i * 32); });
+    HIP_CHECK(hipStreamSynchronize(s));
+    std::vector<uint8_t> hss(count * 32);
+    const uint8_t* zz = hsk_tail.data() + 32;
+    for (size_t i = 0; i < count; ++i) {
+      uint8_t buf[64];
+      const uint8_t rej = (uint8_t)(0u - (uint32_t)(hflags[i] != 0));
+      for (int k = 0; k < 32; ++k)
+        buf[k] = (uint8_t)((hkp[i * 32 + k] & (uint8_t)~rej) | (zz[k] & rej));
+      memcpy(buf + 32, hhct.data() + i * 32, 32);
+      sha3_256(buf, 64, hss.data() + i * 32);
+    }
+    if (oss.host) {
+      memcpy(ss, hss.data(), hss.size());
+      oss.bytes = 0;
+    } else {
+      HIP_CHECK(hipMemcpyAsync(oss.dev, hss.data(), hss.size(), hipMemcpyHostToDevice, s));
+      HIP_CHECK(hipStreamSynchronize(s));
+    }
+  } else {
+    HIP_CHECK(launch_fo_coins((int)count, dsk + off_pkh, dmu2, mb, (int)mb, dcoins, dkp, s));
+    HIP_CHECK(launch_expand_keys(dcoins, 16, (int)count, c->d_T0, drk, s));
+    HIP_CHECK(launch_fill_u32(dflags, count, 0, s));
+    LWE_CHECK(encrypt_core(c, pid, p, count, dsk + off_pk, drk, dmu2, mb, nullptr, dct, dflags, s));
+    uint8_t* dhct;
+    LWE_CHECK(ensure_t(c, B_HCT, count * 32, &dhct));
+    HIP_CHECK(launch_hash_records((int)count, dct, p.ct_bytes, p.ct_bytes, dhct, s));
+    HIP_CHECK(launch_final_ss((int)count, dflags, dkp, dsk + off_z, dhct, oss.dev, s));
+  }
+  LWE_CHECK(finish_out(oss, s));
+  if (oss.host || !stream) HIP_CHECK(hipStreamSynchronize(s));
+  return LWE_OK;
+}
+
+int lwe_decaps(lwe_ctx* c, int pid, const uint8_t* sk, const uint8_t* ct, uint8_t* ss, void* stream) {
+  return lwe_decaps_batch(c, pid, 1, sk, ct, ss, stream);
+}
+
+// ---------------------------------------------------------------------------------------
+// Test hooks
+// ---------------------------------------------------------------------------------------
+int lwe_test_expand_A(lwe_ctx* c, int pid, const uint8_t* seedA, uint32_t col0, uint32_t ncols,
+                      uint16_t* out, void* stream) {
+  const Params* pp;
+  if (!c || !seedA || !out) return LWE_EINVAL;
+  LWE_CHECK(check_pid(pid, &pp));
+  const Params& p = *pp;
+  if ((uint64_t)col0 + ncols > (uint64_t)p.n) return LWE_EINVAL;
+  DevGuard g(c->device);
+  hipStream_t s = pick_stream(c, stream);
+  const uint8_t* dA;
+  LWE_CHECK(stage_in(c, B_SEEDA, seedA, 16, s, &dA));
+  uint32_t* rk;
+  LWE_CHECK(ensure_t(c, B_RKA, 44 * 4, &rk));
+  HIP_CHECK(launch_expand_keys(dA, 16, 1, c->d_T0, rk, s));
+  OutStage o;
+  LWE_CHECK(stage_out(c, B_TEST, out, (size_t)ncols * p.n * 2, o));
+  HIP_CHECK(launch_expand_A(p, rk, c->d_T0, col0, ncols, (uint16_t*)o.dev, s));
+  LWE_CHECK(finish_out(o, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  return LWE_OK;
+}
+
+int lwe_test_keystream(lwe_ctx* c, const uint8_t* key, uint32_t domain, uint64_t block0, size_t nblocks,
+                       uint8_t* out, void* stream) {
+  if (!c || !key || !out) return LWE_EINVAL;
+  DevGuard g(c->device);
+  hipStream_t s = pick_stream(c, stream);
+  const uint8_t* dk;
+  LWE_CHECK(stage_in(c, B_SEEDA, key, 16, s, &dk));
+  uint32_t* rk;
+  LWE_CHECK(ensure_t(c, B_RKA, 44 * 4, &rk));
+  HIP_CHECK(launch_expand_keys(dk, 16, 1, c->d_T0, rk, s));
+  OutStage o;
+  LWE_CHECK(stage_out(c, B_TEST, out, nblocks * 16, o));
+  HIP_CHECK(launch_keystream(rk, c->d_T0, domain, block0, nblocks, o.dev, s));
+  LWE_CHECK(finish_out(o, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  return LWE_OK;
+}
+
+int lwe_test_sample(lwe_ctx* c, int pid, const uint8_t* key, uint32_t domain, uint64_t word0, size_t count,
+                    int16_t* out, void* stream) {
+  const Params* pp;
+  if (!c || !key || !out) return LWE_EINVAL;
+  LWE_CHECK(check_pid(pid, &pp));
+  DevGuard g(c->device);
+  hipStream_t s = pick_stream(c, stream);
+  const uint8_t* dk;
+  LWE_CHECK(stage_in(c, B_SEEDA, key, 16, s, &dk));
+  uint32_t* rk;
+  LWE_CHECK(ensure_t(c, B_RKA, 44 * 4, &rk));
+  HIP_CHECK(launch_expand_keys(dk, 16, 1, c->d_T0, rk, s));
+  OutStage o;
+  LWE_CHECK(stage_out(c, B_TEST, out, count * 2, o));
+  HIP_CHECK(launch_sample_stream(*pp, rk, c->d_T0, domain, word0, count, (int16_t*)o.dev, s));
+  LWE_CHECK(finish_out(o, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  return LWE_OK;
+}
+
+int lwe_test_encrypt(lwe_ctx* c, int pid, size_t count, const uint8_t* pk, const uint8_t* coins,
+                     const uint8_t* mu, uint8_t* ct, void* stream) {
+  const Params* pp;
+  if (!c || !pk || !coins || !mu || !ct || count > LWE_MAX_BATCH) return LWE_EINVAL;
+  LWE_CHECK(check_pid(pid, &pp));
+  if (count == 0) return LWE_OK;
+  const Params& p = *pp;
+  DevGuard g(c->device);
+  hipStream_t s = pick_stream(c, stream);
+  const uint8_t *dpk, *dco, *dmu;
+  LWE_CHECK(stage_in(c, B_PK, pk, p.pk_bytes, s, &dpk));
+  LWE_CHECK(stage_in(c, B_SEEDSK, coins, count * 16, s, &dco));
+  LWE_CHECK(stage_in(c, B_MU, mu, count * p.mu_bytes, s, &dmu));
+  OutStage o;
+  LWE_CHECK(stage_out(c, B_CT, ct, count * p.ct_bytes, o));
+  uint32_t* drk;
+  LWE_CHECK(ensure_t(c, B_RK, count * 44 * 4, &drk));
+  HIP_CHECK(launch_expand_keys(dco, 16, (int)count, c->d_T0, drk, s));
+  LWE_CHECK(encrypt_core(c, pid, p, count, dpk, drk, dmu, p.mu_bytes, o.dev, nullptr, nullptr, s));
+  LWE_CHECK(finish_out(o, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  return LWE_OK;
+}
+
+int lwe_test_decrypt(lwe_ctx* c, int pid, size_t count, const uint8_t* sk, const uint8_t* ct, uint8_t* mu,
+                     void* stream) {
+  const Params* pp;
+  if (!c || !sk || !ct || !mu || count > LWE_MAX_BATCH) return LWE_EINVAL;
+  LWE_CHECK(check_pid(pid, &pp));
+  if (count == 0) return LWE_OK;
+  const Params& p = *pp;
+  DevGuard g(c->device);
+  hipStream_t s = pick_stream(c, stream);
+  const uint8_t *dsk, *dct;
+  LWE_CHECK(stage_in(c, B_SK, sk, p.sk_bytes, s, &dsk));
+  LWE_CHECK(stage_in(c, B_CT, ct, count * p.ct_bytes, s, &dct));
+  OutStage o;
+  LWE_CHECK(stage_out(c, B_MU2, mu, count * p.mu_bytes, o));
+  DecArgs da;
+  da.ct = dct;
+  da.ct_stride = p.ct_bytes;
+  da.St16 = dsk;
+  da.n = p.n;
+  da.logq = p.logq;
+  da.B = p.B;
+  da.count = (int)count;
+  da.mu_bytes = (int)p.mu_bytes;
+  da.mu_out = o.dev;
+  HIP_CHECK(launch_decrypt(da, s));
+  LWE_CHECK(finish_out(o, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  return LWE_OK;
+}
+
+int lwe_test_sha3(lwe_ctx* c, size_t count, size_t len, const uint8_t* in, uint8_t* out, void* stream) {
+  if (!c || !in || !out || count > ((size_t)1 << 24)) return LWE_EINVAL;
+  if (count == 0) return LWE_OK;
+  DevGuard g(c->device);
+  hipStream_t s = pick_stream(c, stream);
+  const uint8_t* din;
+  LWE_CHECK(stage_in(c, B_CT, in, count * len, s, &din));
+  OutStage o;
+  LWE_CHECK(stage_out(c, B_TEST, out, count * 32, o));
+  HIP_CHECK(launch_hash_records((int)count, din, len, len, o.dev, s));
+  LWE_CHECK(finish_out(o, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  return LWE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,934 @@
+// HIP kernels (gfx950) of the plain-LWE KEM hot path.
+//
+//  * AES-128-CTR with T-tables in LDS: the seed expansion sample(rho) of Alg. 1 that yields
+//    the public matrix A, and the device-side noise source of Sec. 3.3.  A is regenerated
+//    tile by tile inside the products (Sec. 3.5) and never written to HBM.
+//  * CDF-table sampling of the secrets and errors (Alg. 1-2).
+//  * The mod-2^16 products B^T = S^T A^T + E^T, B' = S' A + E', V = S' B + E'' + enc(mu)
+//    (Alg. 1-2) and M = V - B' S (Alg. 3) on int8 MFMA: each 16-bit operand is split into two
+//    signed 8-bit limbs x = lo + 256 hi (mod 2^16), both limbs are multiplied against the
+//    small int8 matrix with int32 accumulation, and lo + 256 hi is reduced mod 2^logq.
+//  * SHA3-256 sponges for the Fujisaki-Okamoto transform (Alg. 4-5).
+#include "lwe_internal.h"
+
+namespace lwe {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef unsigned short v2u16 __attribute__((ext_vector_type(2)));
+
+// ======================================================================================
+// AES-128 with T-tables in LDS.  T[0..255] = T0, T[256..] = T0 rotated by 8, 16, 24.
+// ======================================================================================
+__device__ __forceinline__ uint32_t rotl32(uint32_t v, int r) { return (v << r) | (v >> (32 - r)); }
+
+__device__ __forceinline__ void load_tables(uint32_t* T, const uint32_t* __restrict__ T0) {
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) {
+    const uint32_t v = T0[i];
+    T[i] = v;
+    T[256 + i] = rotl32(v, 8);
+    T[512 + i] = rotl32(v, 16);
+    T[768 + i] = rotl32(v, 24);
+  }
+}
+
+// Encrypts the CTR counter block of domain `dom` (as its little-endian word) and block
+// index b: the 128-bit big-endian integer dom * 2^96 + b.
+template <class RK>
+__device__ __forceinline__ void aes_ctr_block(const uint32_t* __restrict__ T, const RK& rk,
+                                              uint32_t dom_le, uint64_t b, uint32_t o[4]) {
+  uint32_t s0 = dom_le ^ rk[0];
+  uint32_t s1 = rk[1];
+  uint32_t s2 = bswap32((uint32_t)(b >> 32)) ^ rk[2];
+  uint32_t s3 = bswap32((uint32_t)b) ^ rk[3];
+#pragma unroll
+  for (int r = 1; r < 10; ++r) {
+    const uint32_t t0 = T[s0 & 0xff] ^ T[256 + ((s1 >> 8) & 0xff)] ^ T[512 + ((s2 >> 16) & 0xff)] ^
+                        T[768 + (s3 >> 24)] ^ rk[4 * r];
+    const uint32_t t1 = T[s1 & 0xff] ^ T[256 + ((s2 >> 8) & 0xff)] ^ T[512 + ((s3 >> 16) & 0xff)] ^
+                        T[768 + (s0 >> 24)] ^ rk[4 * r + 1];
+    const uint32_t t2 = T[s2 & 0xff] ^ T[256 + ((s3 >> 8) & 0xff)] ^ T[512 + ((s0 >> 16) & 0xff)] ^
+                        T[768 + (s1 >> 24)] ^ rk[4 * r + 2];
+    const uint32_t t3 = T[s3 & 0xff] ^ T[256 + ((s0 >> 8) & 0xff)] ^ T[512 + ((s1 >> 16) & 0xff)] ^
+                        T[768 + (s2 >> 24)] ^ rk[4 * r + 3];
+    s0 = t0;
+    s1 = t1;
+    s2 = t2;
+    s3 = t3;
+  }
+  // Final round (no MixColumns): the S-box value of x sits in byte 0 of T2[x], byte 1 of
+  // T3[x], byte 2 of T0[x] and byte 3 of T1[x].
+  o[0] = ((T[512 + (s0 & 0xff)] & 0xffu) | (T[768 + ((s1 >> 8) & 0xff)] & 0xff00u) |
+          (T[(s2 >> 16) & 0xff] & 0xff0000u) | (T[256 + (s3 >> 24)] & 0xff000000u)) ^
+         rk[40];
+  o[1] = ((T[512 + (s1 & 0xff)] & 0xffu) | (T[768 + ((s2 >> 8) & 0xff)] & 0xff00u) |
+          (T[(s3 >> 16) & 0xff] & 0xff0000u) | (T[256 + (s0 >> 24)] & 0xff000000u)) ^
+         rk[41];
+  o[2] = ((T[512 + (s2 & 0xff)] & 0xffu) | (T[768 + ((s3 >> 8) & 0xff)] & 0xff00u) |
+          (T[(s0 >> 16) & 0xff] & 0xff0000u) | (T[256 + (s1 >> 24)] & 0xff000000u)) ^
+         rk[42];
+  o[3] = ((T[512 + (s3 & 0xff)] & 0xffu) | (T[768 + ((s0 >> 8) & 0xff)] & 0xff00u) |
+          (T[(s1 >> 16) & 0xff] & 0xff0000u) | (T[256 + (s2 >> 24)] & 0xff000000u)) ^
+         rk[43];
+}
+
+// ======================================================================================
+// Limb split: a 16-bit value x (already reduced mod q) equals lo + 256 hi (mod 2^16) with
+// lo = sext8(x & 0xff) and hi = sext8(((x + 0x80) >> 8) & 0xff).  The int8 byte of lo is the
+// low byte of x itself.
+// ======================================================================================
+__device__ __forceinline__ uint32_t pk_add_u16(uint32_t a, uint32_t b) {
+  v2u16 va = __builtin_bit_cast(v2u16, a), vb = __builtin_bit_cast(v2u16, b);
+  return __builtin_bit_cast(uint32_t, va + vb);
+}
+
+// two words holding four uint16 values -> four lo bytes and four hi bytes
+__device__ __forceinline__ void limbs4(uint32_t a, uint32_t b, uint32_t& lo, uint32_t& hi) {
+  lo = __builtin_amdgcn_perm(b, a, 0x06040200u);
+  const uint32_t a2 = pk_add_u16(a, 0x00800080u), b2 = pk_add_u16(b, 0x00800080u);
+  hi = __builtin_amdgcn_perm(b2, a2, 0x07050301u);
+}
+
+__device__ __forceinline__ uint32_t sample_one(uint32_t u, const uint16_t* T, int K) {
+  const uint32_t r = u >> 1;
+  int e = 0;
+#pragma unroll
+  for (int k = 0; k < MAX_K; ++k)
+    if (k < K) e += (r > T[k]) ? 1 : 0;
+  return (uint32_t)(uint8_t)(int8_t)((u & 1) ? -e : e);
+}
+
+// ======================================================================================
+// Small utility kernels
+// ======================================================================================
+__global__ void k_fill_u32(uint32_t* p, size_t count, uint32_t v) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < count; i += stride) p[i] = v;
+}
+
+// FIPS-197 key expansion, one key per thread; the S-box comes from byte 1 of T0.
+__global__ void k_expand_keys(const uint8_t* __restrict__ keys, size_t key_stride, int count,
+                              const uint32_t* __restrict__ T0, uint32_t* __restrict__ rk_out) {
+  __shared__ uint8_t sb[256];
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) sb[i] = (uint8_t)(T0[i] >> 8);
+  __syncthreads();
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  uint8_t key[16];
+  for (int b = 0; b < 16; ++b) key[b] = keys[(size_t)k * key_stride + b];
+  uint32_t rk[44];
+  aes128_key_schedule(key, sb, rk);
+  for (int w = 0; w < 44; ++w) rk_out[(size_t)k * 44 + w] = rk[w];
+}
+
+__global__ void k_keystream(const uint32_t* __restrict__ rk, const uint32_t* __restrict__ T0,
+                            uint32_t dom_le, uint64_t block0, size_t nblocks, uint8_t* out) {
+  __shared__ uint32_t T[1024];
+  load_tables(T, T0);
+  __syncthreads();
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nblocks) return;
+  uint32_t o[4];
+  aes_ctr_block(T, rk, dom_le, block0 + t, o);
+  uint4 v = make_uint4(o[0], o[1], o[2], o[3]);
+  *(uint4*)(out + 16 * t) = v;
+}
+
+// A[i][j] = keystream word (j n + i) of domain 0 under seedA, masked to logq bits.
+__global__ void k_expand_A(int n, uint32_t qmask2, const uint32_t* __restrict__ rk,
+                           const uint32_t* __restrict__ T0, uint32_t col0, uint32_t ncols,
+                           uint16_t* out) {
+  __shared__ uint32_t T[1024];
+  load_tables(T, T0);
+  __syncthreads();
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t bpc = (size_t)n / 8;
+  if (t >= (size_t)ncols * bpc) return;
+  const size_t c = t / bpc, kb = t % bpc;
+  const uint64_t b = ((uint64_t)col0 + c) * bpc + kb;
+  uint32_t o[4];
+  aes_ctr_block(T, rk, 0u, b, o);
+  uint4 v = make_uint4(o[0] & qmask2, o[1] & qmask2, o[2] & qmask2, o[3] & qmask2);
+  *(uint4*)(out + c * n + 8 * kb) = v;
+}
+
+struct SampTable {
+  uint16_t T[MAX_K + 1];
+};
+
+__global__ void k_sample_stream(SampTable st, int K, const uint32_t* __restrict__ rk,
+                                const uint32_t* __restrict__ T0, uint32_t dom_le, uint64_t word0,
+                                size_t count, int16_t* out) {
+  __shared__ uint32_t T[1024];
+  load_tables(T, T0);
+  __syncthreads();
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  const uint64_t w = word0 + t;
+  uint32_t o[4];
+  aes_ctr_block(T, rk, dom_le, w / 8, o);
+  const uint32_t u = (o[(w % 8) >> 1] >> (16 * (w & 1))) & 0xffffu;
+  out[t] = (int16_t)(int8_t)(uint8_t)sample_one(u, st.T, K);
+}
+
+// ======================================================================================
+// Sampling of the secrets and errors of one KeyGen (S^T, E^T) or Encrypt (S', E', E'') per
+// instance.  Keystream domains: 1 -> segment 0, 2 -> segment 1, 3 -> segment 2.  Every AES
+// block gives 8 consecutive samples of one matrix row.
+// ======================================================================================
+__global__ void __launch_bounds__(256) k_sample(SampleArgs a) {
+  __shared__ uint32_t T[1024];
+  const int inst = blockIdx.y;
+  const uint32_t* __restrict__ rk = a.rk + (size_t)inst * 44;
+  load_tables(T, a.T0);
+  const int n = a.n;
+  if (blockIdx.x == 0 && a.ldx > n) {  // zero the padding columns of segment 0
+    const int pad = a.ldx - n;
+    for (int idx = threadIdx.x; idx < 8 * pad; idx += blockDim.x)
+      a.X[((size_t)inst * 8 + idx / pad) * a.ldx + n + idx % pad] = 0;
+  }
+  __syncthreads();
+  const int total = 2 * n + (a.nseg == 3 ? 8 : 0);
+  const int t_end = min(total, (int)(blockIdx.x + 1) * a.chunk);
+  for (int t = blockIdx.x * a.chunk + threadIdx.x; t < t_end; t += blockDim.x) {
+    int seg, lb;
+    if (t < n) {
+      seg = 0;
+      lb = t;
+    } else if (t < 2 * n) {
+      seg = 1;
+      lb = t - n;
+    } else {
+      seg = 2;
+      lb = t - 2 * n;
+    }
+    uint32_t o[4];
+    aes_ctr_block(T, rk, bswap32((uint32_t)(seg + 1)), (uint64_t)lb, o);
+    uint32_t e[8];
+#pragma unroll
+    for (int w = 0; w < 8; ++w) e[w] = sample_one((o[w >> 1] >> (16 * (w & 1))) & 0xffffu, a.T, a.K);
+    const uint32_t p0 = e[0] | (e[1] << 8) | (e[2] << 16) | (e[3] << 24);
+    const uint32_t p1 = e[4] | (e[5] << 8) | (e[6] << 16) | (e[7] << 24);
+    const int w0 = 8 * lb;
+    if (seg == 0) {
+      const int row = w0 / n, col = w0 % n;
+      *(uint2*)(a.X + ((size_t)inst * 8 + row) * a.ldx + col) = make_uint2(p0, p1);
+      if (a.X16) {
+        uint32_t h[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const uint32_t lo = (uint32_t)(uint16_t)(int16_t)(int8_t)(uint8_t)e[2 * k];
+          const uint32_t hi = (uint32_t)(uint16_t)(int16_t)(int8_t)(uint8_t)e[2 * k + 1];
+          h[k] = lo | (hi << 16);
+        }
+        *(uint4*)(a.X16 + (size_t)inst * a.x16_stride + 2 * ((size_t)row * n + col)) =
+            make_uint4(h[0], h[1], h[2], h[3]);
+      }
+    } else if (seg == 1) {
+      const int row = w0 / n, col = w0 % n;
+      *(uint2*)(a.E + ((size_t)inst * 8 + row) * n + col) = make_uint2(p0, p1);
+    } else {
+      *(uint2*)(a.E2 + (size_t)inst * 64 + w0) = make_uint2(p0, p1);
+    }
+  }
+}
+
+// ======================================================================================
+// Product epilogue: reduce D mod q, add the error (and for V the encoded message), then
+// store, compare with a received ciphertext, or accumulate a split-K partial.
+// ======================================================================================
+__device__ __forceinline__ uint32_t encode_coeff(const uint8_t* mu, int mu_bytes, int B, int logq,
+                                                 int coeff) {
+  const int bit = coeff * B, byte = bit >> 3, sh = bit & 7;
+  uint32_t v = mu[byte];
+  if (byte + 1 < mu_bytes) v |= (uint32_t)mu[byte + 1] << 8;
+  return ((v >> sh) & ((1u << B) - 1u)) << (logq - B);
+}
+
+// value of output element (row, col) of the encryption / keygen layouts, and its byte
+// offset inside the record
+__device__ __forceinline__ void epi_value(const ProdArgs& a, int row, int col, uint32_t D,
+                                          uint32_t& val, size_t& off) {
+  const int inst = row >> 3, r = row & 7, n = a.n;
+  const uint32_t qmask = (1u << a.logq) - 1u;
+  if (col < n) {
+    val = (D + (uint32_t)(int32_t)a.E[(size_t)row * n + col]) & qmask;
+    off = a.out_off + 2 * ((size_t)r * n + col);
+  } else {
+    const int c = col - n;
+    const int mb = 8 * a.B;
+    val = (D + (uint32_t)(int32_t)a.E2[(size_t)inst * 64 + r * 8 + c] +
+           encode_coeff(a.mu + (size_t)inst * a.mu_stride, mb, a.B, a.logq, r * 8 + c)) &
+          qmask;
+    off = 2 * ((size_t)8 * n + r * 8 + c);
+  }
+}
+
+// Finalises one element; returns 1 if (compare mode) it differs from the received ct.
+__device__ __forceinline__ uint32_t epi_store(const ProdArgs& a, int row, int col, uint32_t D) {
+  uint32_t val;
+  size_t off;
+  epi_value(a, row, col, D, val, off);
+  const int inst = row >> 3;
+  if (a.mode == PM_COMPARE) {
+    const uint16_t got = *(const uint16_t*)(a.cmp + (size_t)inst * a.cmp_stride + off);
+    return got != (uint16_t)val ? 1u : 0u;
+  }
+  *(uint16_t*)(a.out + (size_t)inst * a.out_stride + off) = (uint16_t)val;
+  return 0u;
+}
+
+// Compare mode: lanes 0-31 of a 16-row MFMA tile hold rows 0-7 (one instance) and lanes
+// 32-63 rows 8-15 (the next one).  One atomic per instance and tile, whatever the data.
+__device__ __forceinline__ void flag_tile(const ProdArgs& a, int row_base, uint32_t mism) {
+  const uint64_t bal = __ballot(mism != 0);
+  const int lane = threadIdx.x & 63;
+  if (lane == 0 && row_base < a.M)
+    atomicOr(&a.flags[row_base >> 3], (uint32_t)((bal & 0xffffffffull) != 0));
+  if (lane == 32 && row_base + 8 < a.M)
+    atomicOr(&a.flags[(row_base >> 3) + 1], (uint32_t)((bal >> 32) != 0));
+}
+
+// ======================================================================================
+// Product, streaming form (small row counts: plain encryption, all key generations).
+// Each wave generates its own A fragments per 64-row contraction step and multiplies them
+// at once; waves of a workgroup split the K chunk and are reduced through LDS.
+//   grid.x = n_jt * n_kc, grid.y = row tiles (or instances when per_inst_A)
+// ======================================================================================
+template <int CG, int RG, bool TRANS>
+__global__ void __launch_bounds__(1024) k_prod_stream(ProdArgs a, int ks_per_wave) {
+  extern __shared__ uint32_t smem[];
+  uint32_t* T = smem;
+  const int W = blockDim.x >> 6;
+  uint32_t* red = smem + 1024;                                  // [W][RG][CG][4][64]
+  uint8_t* tr = (uint8_t*)(red + (size_t)W * RG * CG * 256);    // TRANS: [W][2][CG][16][64]
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int jt = blockIdx.x % a.n_jt, kc = blockIdx.x / a.n_jt, mt = blockIdx.y;
+  const uint32_t* __restrict__ rk = a.rkA + (a.per_inst_A ? (size_t)mt * 44 : 0);
+  const int n = a.n;
+  const int m_begin = mt * a.m_tile, m_end = min(a.M, m_begin + a.m_tile);
+  const int nn0 = jt * 16 * CG;
+  const uint32_t qmask2 = ((1u << a.logq) - 1u) * 0x10001u;
+  const int k_chunk0 = kc * a.kc_len;
+
+  load_tables(T, a.T0);
+  __syncthreads();
+
+  v4i acc[RG][CG][2];
+#pragma unroll
+  for (int rg = 0; rg < RG; ++rg)
+#pragma unroll
+    for (int cg = 0; cg < CG; ++cg) acc[rg][cg][0] = acc[rg][cg][1] = v4i{0, 0, 0, 0};
+
+  for (int st = 0; st < ks_per_wave; ++st) {
+    const int kbase = k_chunk0 + (wave * ks_per_wave + st) * 64;
+    const bool kvalid = kbase < n && (wave * ks_per_wave + st) * 64 < a.kc_len;
+    v4i xf[RG];
+#pragma unroll
+    for (int rg = 0; rg < RG; ++rg) {
+      const int row = m_begin + rg * 16 + (lane & 15);
+      const int k = kbase + 16 * (lane >> 4);
+      if (kvalid && row < m_end)
+        xf[rg] = *(const v4i*)(a.X + (size_t)row * a.ldx + k);
+      else
+        xf[rg] = v4i{0, 0, 0, 0};
+    }
+    v4i yf[CG][2];
+    if constexpr (!TRANS) {
+#pragma unroll
+      for (int cg = 0; cg < CG; ++cg) {
+        const int col = nn0 + cg * 16 + (lane & 15);
+        const int k = kbase + 16 * (lane >> 4);
+        uint32_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (kvalid && k < n) {
+          if (col < n) {
+            const uint64_t b = ((uint64_t)col * n + k) >> 3;
+            aes_ctr_block(T, rk, 0u, b, w);
+            if (k + 8 < n) aes_ctr_block(T, rk, 0u, b + 1, w + 4);
+          } else if (col < n + 8 && a.Bt) {
+            const uint4 v0 = *(const uint4*)(a.Bt + 2 * ((size_t)(col - n) * n + k));
+            w[0] = v0.x; w[1] = v0.y; w[2] = v0.z; w[3] = v0.w;
+            if (k + 8 < n) {
+              const uint4 v1 = *(const uint4*)(a.Bt + 2 * ((size_t)(col - n) * n + k + 8));
+              w[4] = v1.x; w[5] = v1.y; w[6] = v1.z; w[7] = v1.w;
+            }
+          }
+        }
+        uint32_t lo[4], hi[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) limbs4(w[2 * q] & qmask2, w[2 * q + 1] & qmask2, lo[q], hi[q]);
+        yf[cg][0] = v4i{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3]};
+        yf[cg][1] = v4i{(int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+      }
+    } else {
+      // lane l owns column j = kbase + l of A and 16 consecutive rows per column group;
+      // the 64 x 16 tile is transposed through this wave's LDS slice.
+      uint8_t* my = tr + (size_t)wave * 2 * CG * 1024;
+      const int j = kbase + lane;
+#pragma unroll
+      for (int cg = 0; cg < CG; ++cg) {
+        const int i0 = nn0 + cg * 16;
+        uint32_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (kvalid && j < n && i0 < n) {
+          const uint64_t b = ((uint64_t)j * n + i0) >> 3;
+          aes_ctr_block(T, rk, 0u, b, w);
+          if (i0 + 8 < n) aes_ctr_block(T, rk, 0u, b + 1, w + 4);
+        }
+        uint32_t lo[4], hi[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) limbs4(w[2 * q] & qmask2, w[2 * q + 1] & qmask2, lo[q], hi[q]);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          my[(0 * CG + cg) * 1024 + r * 64 + lane] = (uint8_t)(lo[r >> 2] >> (8 * (r & 3)));
+          my[(1 * CG + cg) * 1024 + r * 64 + lane] = (uint8_t)(hi[r >> 2] >> (8 * (r & 3)));
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int cg = 0; cg < CG; ++cg)
+#pragma unroll
+        for (int limb = 0; limb < 2; ++limb)
+          yf[cg][limb] = *(const v4i*)(my + (limb * CG + cg) * 1024 + (lane & 15) * 64 +
+                                       16 * (lane >> 4));
+      __syncthreads();
+    }
+#pragma unroll
+    for (int rg = 0; rg < RG; ++rg)
+#pragma unroll
+      for (int cg = 0; cg < CG; ++cg)
+#pragma unroll
+        for (int limb = 0; limb < 2; ++limb)
+          acc[rg][cg][limb] =
+              __builtin_amdgcn_mfma_i32_16x16x64_i8(xf[rg], yf[cg][limb], acc[rg][cg][limb], 0, 0, 0);
+  }
+
+  // recombine limbs; reduce the waves' partial sums through LDS
+  uint32_t D[RG][CG][4];
+#pragma unroll
+  for (int rg = 0; rg < RG; ++rg)
+#pragma unroll
+    for (int cg = 0; cg < CG; ++cg)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        D[rg][cg][i] = (uint32_t)acc[rg][cg][0][i] + ((uint32_t)acc[rg][cg][1][i] << 8);
+  if (W > 1) {
+#pragma unroll
+    for (int rg = 0; rg < RG; ++rg)
+#pragma unroll
+      for (int cg = 0; cg < CG; ++cg)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          red[(((size_t)wave * RG + rg) * CG + cg) * 256 + i * 64 + lane] = D[rg][cg][i];
+    __syncthreads();
+    if (wave != 0) return;
+    for (int w = 1; w < W; ++w)
+#pragma unroll
+      for (int rg = 0; rg < RG; ++rg)
+#pragma unroll
+        for (int cg = 0; cg < CG; ++cg)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            D[rg][cg][i] += red[(((size_t)w * RG + rg) * CG + cg) * 256 + i * 64 + lane];
+  }
+#pragma unroll
+  for (int rg = 0; rg < RG; ++rg) {
+    uint32_t mism = 0;
+    const int row_base = m_begin + rg * 16;
+#pragma unroll
+    for (int cg = 0; cg < CG; ++cg)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = row_base + 4 * (lane >> 4) + i;
+        const int col = nn0 + cg * 16 + (lane & 15);
+        if (row >= m_end || col >= a.ncols) continue;
+        if (a.n_kc > 1)
+          atomicAdd((uint32_t*)&a.acc32[(size_t)row * a.acc_ld + col], D[rg][cg][i]);
+        else
+          mism |= epi_store(a, row, col, D[rg][cg][i]);
+      }
+    if (a.mode == PM_COMPARE && a.n_kc == 1) flag_tile(a, row_base, mism);
+  }
+}
+
+// ======================================================================================
+// Product, strip form (large row counts: batched encryption against one public key).
+// The workgroup regenerates a strip of A (all contraction rows of the K chunk x 16*CG
+// columns) into LDS once, already split into limbs and laid out as MFMA B fragments, and
+// then streams every row tile of its row chunk through it.
+//   LDS: [ksteps][CG][limb][64 lanes][16 bytes] after the 4 KB of AES tables.
+// Workgroup ids are remapped so that each XCD (ids congruent mod 8) processes a
+// contiguous range of tiles, i.e. the same row chunks share that XCD's L2.
+// ======================================================================================
+template <int CG, int RG>
+__global__ void __launch_bounds__(256) k_prod_strip(ProdArgs a) {
+  extern __shared__ uint32_t smem[];
+  uint32_t* T = smem;
+  uint8_t* strip = (uint8_t*)(smem + 1024);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int total = a.n_jt * a.n_kc * a.n_mt;
+  const int per = (total + 7) / 8;
+  const int v = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (v >= total) return;
+  const int jt = v % a.n_jt;
+  const int kc = (v / a.n_jt) % a.n_kc;
+  const int mt = v / (a.n_jt * a.n_kc);
+  const int n = a.n;
+  const int nn0 = jt * 16 * CG;
+  const int k0 = kc * a.kc_len;
+  const int k_len = min(a.kc_len, n - k0);
+  const int ksteps = (k_len + 63) >> 6;
+  const uint32_t qmask2 = ((1u << a.logq) - 1u) * 0x10001u;
+  const uint32_t* __restrict__ rk = a.rkA;
+
+  load_tables(T, a.T0);
+  __syncthreads();
+
+  // ---- regenerate the strip ----
+  const int items = 16 * CG * ksteps * 8;
+  for (int t = threadIdx.x; t < items; t += blockDim.x) {
+    const int col_local = t / (ksteps * 8), kb = t % (ksteps * 8);
+    const int k = k0 + 8 * kb, col = nn0 + col_local;
+    uint32_t w[4] = {0, 0, 0, 0};
+    if (k < k0 + k_len) {
+      if (col < n) {
+        aes_ctr_block(T, rk, 0u, ((uint64_t)col * n + k) >> 3, w);
+      } else if (col < n + 8 && a.Bt) {
+        const uint4 bv = *(const uint4*)(a.Bt + 2 * ((size_t)(col - n) * n + k));
+        w[0] = bv.x; w[1] = bv.y; w[2] = bv.z; w[3] = bv.w;
+      }
+    }
+    uint32_t lo0, hi0, lo1, hi1;
+    limbs4(w[0] & qmask2, w[1] & qmask2, lo0, hi0);
+    limbs4(w[2] & qmask2, w[3] & qmask2, lo1, hi1);
+    const int s = kb >> 3, g = (kb & 7) >> 1, h = kb & 1;
+    const int lane_t = g * 16 + (col_local & 15), cg = col_local >> 4;
+    uint8_t* base = strip + ((size_t)((s * CG + cg) * 2) * 64 + lane_t) * 16 + h * 8;
+    *(uint2*)base = make_uint2(lo0, lo1);
+    *(uint2*)(base + 64 * 16) = make_uint2(hi0, hi1);
+  }
+  __syncthreads();
+
+  // ---- stream the row tiles ----
+  const int m_begin = mt * a.m_tile, m_end = min(a.M, m_begin + a.m_tile);
+  const int rows = m_end - m_begin;
+  const int nrb = (rows + 16 * RG - 1) / (16 * RG);
+  for (int rb = wave; rb < nrb; rb += 4) {
+    v4i acc[RG][CG][2];
+#pragma unroll
+    for (int rg = 0; rg < RG; ++rg)
+#pragma unroll
+      for (int cg = 0; cg < CG; ++cg) acc[rg][cg][0] = acc[rg][cg][1] = v4i{0, 0, 0, 0};
+    const int rbase = m_begin + rb * 16 * RG;
+    const int8_t* xp[RG];
+    bool xv[RG];
+#pragma unroll
+    for (int rg = 0; rg < RG; ++rg) {
+      const int row = rbase + rg * 16 + (lane & 15);
+      xv[rg] = row < m_end;
+      xp[rg] = a.X + (size_t)(xv[rg] ? row : m_begin) * a.ldx + k0 + 16 * (lane >> 4);
+    }
+    v4i xf[RG], xn[RG];
+#pragma unroll
+    for (int rg = 0; rg < RG; ++rg) xf[rg] = xv[rg] ? *(const v4i*)xp[rg] : v4i{0, 0, 0, 0};
+    for (int s = 0; s < ksteps; ++s) {
+      if (s + 1 < ksteps) {
+#pragma unroll
+        for (int rg = 0; rg < RG; ++rg)
+          xn[rg] = xv[rg] ? *(const v4i*)(xp[rg] + 64 * (s + 1)) : v4i{0, 0, 0, 0};
+      }
+#pragma unroll
+      for (int cg = 0; cg < CG; ++cg) {
+        const v4i ylo = *(const v4i*)(strip + ((size_t)((s * CG + cg) * 2) * 64 + lane) * 16);
+        const v4i yhi = *(const v4i*)(strip + ((size_t)((s * CG + cg) * 2 + 1) * 64 + lane) * 16);
+#pragma unroll
+        for (int rg = 0; rg < RG; ++rg) {
+          acc[rg][cg][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(xf[rg], ylo, acc[rg][cg][0], 0, 0, 0);
+          acc[rg][cg][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(xf[rg], yhi, acc[rg][cg][1], 0, 0, 0);
+        }
+      }
+      if (s + 1 < ksteps) {
+#pragma unroll
+        for (int rg = 0; rg < RG; ++rg) xf[rg] = xn[rg];
+      }
+    }
+#pragma unroll
+    for (int rg = 0; rg < RG; ++rg) {
+      uint32_t mism = 0;
+      const int row_base = rbase + rg * 16;
+#pragma unroll
+      for (int cg = 0; cg < CG; ++cg)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = row_base + 4 * (lane >> 4) + i;
+          const int col = nn0 + cg * 16 + (lane & 15);
+          if (row >= m_end || col >= a.ncols) continue;
+          const uint32_t D = (uint32_t)acc[rg][cg][0][i] + ((uint32_t)acc[rg][cg][1][i] << 8);
+          if (a.n_kc > 1)
+            atomicAdd((uint32_t*)&a.acc32[(size_t)row * a.acc_ld + col], D);
+          else
+            mism |= epi_store(a, row, col, D);
+        }
+      if (a.mode == PM_COMPARE && a.n_kc == 1) flag_tile(a, row_base, mism);
+    }
+  }
+}
+
+// Completes split-K products: acc32 holds the full D for every (row, col).
+__global__ void k_finalize(ProdArgs a) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t total = (size_t)a.M * a.ncols;
+  const bool valid = t < total;
+  const int row = valid ? (int)(t / a.ncols) : 0, col = valid ? (int)(t % a.ncols) : 0;
+  uint32_t mism = 0;
+  if (valid) mism = epi_store(a, row, col, (uint32_t)a.acc32[(size_t)row * a.acc_ld + col]);
+  if (a.mode == PM_COMPARE) {
+    // a wave covers at most two instances (ncols >= 16 and 8 rows per instance)
+    const int lane = threadIdx.x & 63;
+    const int inst = valid ? row >> 3 : -1;
+    const int inst0 = __shfl(inst, 0);
+    const uint64_t b0 = __ballot(mism != 0 && inst == inst0);
+    const uint64_t b1 = __ballot(mism != 0 && inst != inst0);
+    int inst_last = inst;
+    for (int off = 32; off > 0; off >>= 1) inst_last = max(inst_last, __shfl_xor(inst_last, off));
+    if (lane == 0 && inst0 >= 0) atomicOr(&a.flags[inst0], (uint32_t)(b0 != 0));
+    if (lane == 0 && inst_last != inst0 && inst_last >= 0)
+      atomicOr(&a.flags[inst_last], (uint32_t)(b1 != 0));
+  }
+}
+
+// ======================================================================================
+// Decryption M = V - B' S (mod q) and decoding (Alg. 3, generalised to B bits per
+// coefficient: nearest multiple of q / 2^B, halves rounded up).
+// One workgroup (4 waves splitting the contraction) per 16 rows = 2 ciphertexts.
+// ======================================================================================
+__global__ void __launch_bounds__(256) k_decrypt(DecArgs a) {
+  __shared__ uint32_t red[4][4][64];
+  __shared__ uint8_t dec[16][8];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int n = a.n;
+  const int inst0 = 2 * blockIdx.x;
+  const int m = lane & 15, g = lane >> 4;
+  const int inst = inst0 + (m >> 3), r = m & 7;
+  const bool rv = inst < a.count;
+  const int c = lane & 15;
+  const int ksteps = (n + 63) >> 6;
+  v4i acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+  for (int s = wave; s < ksteps; s += 4) {
+    const int k = s * 64 + 16 * g;
+    uint32_t bw[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint32_t sw[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (rv && k < n) {
+      const uint8_t* p = a.ct + (size_t)inst * a.ct_stride + 2 * ((size_t)r * n + k);
+      const uint4 v0 = *(const uint4*)p;
+      bw[0] = v0.x; bw[1] = v0.y; bw[2] = v0.z; bw[3] = v0.w;
+      if (k + 8 < n) {
+        const uint4 v1 = *(const uint4*)(p + 16);
+        bw[4] = v1.x; bw[5] = v1.y; bw[6] = v1.z; bw[7] = v1.w;
+      }
+    }
+    if (c < 8 && k < n) {
+      const uint8_t* p = a.St16 + 2 * ((size_t)c * n + k);
+      const uint4 v0 = *(const uint4*)p;
+      sw[0] = v0.x; sw[1] = v0.y; sw[2] = v0.z; sw[3] = v0.w;
+      if (k + 8 < n) {
+        const uint4 v1 = *(const uint4*)(p + 16);
+        sw[4] = v1.x; sw[5] = v1.y; sw[6] = v1.z; sw[7] = v1.w;
+      }
+    }
+    uint32_t xlo[4], xhi[4], y[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      limbs4(bw[2 * q], bw[2 * q + 1], xlo[q], xhi[q]);
+      y[q] = __builtin_amdgcn_perm(sw[2 * q + 1], sw[2 * q], 0x06040200u);  // int16 -> int8
+    }
+    const v4i yf = {(int)y[0], (int)y[1], (int)y[2], (int)y[3]};
+    acc0 = __builtin_amdgcn_mfma_i32_16x16x64_i8(v4i{(int)xlo[0], (int)xlo[1], (int)xlo[2], (int)xlo[3]},
+                                                 yf, acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(v4i{(int)xhi[0], (int)xhi[1], (int)xhi[2], (int)xhi[3]},
+                                                 yf, acc1, 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) red[wave][i][lane] = (uint32_t)acc0[i] + ((uint32_t)acc1[i] << 8);
+  __syncthreads();
+  if (wave == 0) {
+    const uint32_t qmask = (1u << a.logq) - 1u;
+    const int sh = a.logq - a.B;
+    const uint32_t half = 1u << (sh - 1);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t D = red[0][i][lane] + red[1][i][lane] + red[2][i][lane] + red[3][i][lane];
+      const int row = 4 * g + i;  // row within the 16-row tile
+      const int ins = inst0 + (row >> 3), rr = row & 7;
+      if (c < 8 && ins < a.count) {
+        const uint16_t V =
+            *(const uint16_t*)(a.ct + (size_t)ins * a.ct_stride + 2 * ((size_t)8 * n + rr * 8 + c));
+        const uint32_t Mv = ((uint32_t)V - D) & qmask;
+        dec[row][c] = (uint8_t)(((Mv + half) & qmask) >> sh);
+      }
+    }
+  }
+  __syncthreads();
+  // assemble message bytes: bit p of the message is bit p % B of coefficient p / B
+  const int mb = a.mu_bytes;
+  if ((int)threadIdx.x < 2 * mb) {
+    const int which = threadIdx.x / mb, byte = threadIdx.x % mb;
+    const int ins = inst0 + which;
+    if (ins < a.count) {
+      uint32_t v = 0;
+      for (int b = 0; b < 8; ++b) {
+        const int p = 8 * byte + b, coeff = p / a.B, bit = p % a.B;
+        v |= (uint32_t)((dec[which * 8 + coeff / 8][coeff % 8] >> bit) & 1u) << b;
+      }
+      a.mu_out[(size_t)ins * mb + byte] = (uint8_t)v;
+    }
+  }
+}
+
+// ======================================================================================
+// SHA3-256 sponges (one message per thread).
+// ======================================================================================
+// coins = H(0x01 || pkh || mu)[0:16], K' = H(pkh || mu)
+__global__ void k_fo_coins(int count, const uint8_t* __restrict__ pkh, const uint8_t* __restrict__ mu,
+                           size_t mu_stride, int mu_bytes, uint8_t* coins, uint8_t* kprime) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  uint8_t h[32], pk[32], m[64];
+  const uint8_t one = 1;
+  for (int k = 0; k < 32; ++k) pk[k] = pkh[k];
+  for (int k = 0; k < mu_bytes; ++k) m[k] = mu[(size_t)i * mu_stride + k];
+  sha3_256_3(&one, 1, pk, 32, m, mu_bytes, h);
+  for (int k = 0; k < 16; ++k) coins[(size_t)i * 16 + k] = h[k];
+  sha3_256_3(pk, 32, m, mu_bytes, nullptr, 0, h);
+  for (int k = 0; k < 32; ++k) kprime[(size_t)i * 32 + k] = h[k];
+}
+
+// SHA3-256 of count records of len bytes; 8-byte loads when the layout allows it.
+__global__ void k_hash_records(int count, const uint8_t* __restrict__ in, size_t stride, size_t len,
+                               uint8_t* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const uint8_t* p = in + (size_t)i * stride;
+  uint64_t a[25];
+#pragma unroll
+  for (int k = 0; k < 25; ++k) a[k] = 0;
+  const bool aligned = (((uintptr_t)p) & 7) == 0;
+  size_t off = 0;
+  for (; off + SHA3_RATE <= len; off += SHA3_RATE) {
+    if (aligned) {
+      const uint64_t* q = (const uint64_t*)(p + off);
+#pragma unroll
+      for (int w = 0; w < SHA3_RATE / 8; ++w) a[w] ^= q[w];
+      keccak_f1600(a);
+    } else {
+      sha3_absorb_full(a, p + off);
+    }
+  }
+  sha3_absorb_last(a, p + off, len - off);
+  uint8_t h[32];
+  sha3_squeeze32(a, h);
+  for (int k = 0; k < 32; ++k) out[(size_t)i * 32 + k] = h[k];
+}
+
+// ss = H(pre || H(ct)) with pre = K' (accepted) or z (rejected), selected without branches.
+__global__ void k_final_ss(int count, const uint32_t* __restrict__ flags, const uint8_t* __restrict__ kprime,
+                           const uint8_t* __restrict__ z, const uint8_t* __restrict__ hct, uint8_t* ss) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const uint8_t rej = flags ? (uint8_t)(0u - (uint32_t)(flags[i] != 0)) : 0;
+  uint8_t buf[64], h[32];
+  for (int k = 0; k < 32; ++k) {
+    const uint8_t zk = z ? z[k] : 0;
+    buf[k] = (uint8_t)((kprime[(size_t)i * 32 + k] & (uint8_t)~rej) | (zk & rej));
+    buf[32 + k] = hct[(size_t)i * 32 + k];
+  }
+  sha3_256(buf, 64, h);
+  for (int k = 0; k < 32; ++k) ss[(size_t)i * 32 + k] = h[k];
+}
+
+// ======================================================================================
+// Launchers
+// ======================================================================================
+static inline unsigned nblk(size_t work, unsigned threads) {
+  return (unsigned)((work + threads - 1) / threads);
+}
+
+hipError_t launch_fill_u32(uint32_t* p, size_t count, uint32_t v, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  unsigned blocks = nblk(count, 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill_u32, dim3(blocks), dim3(256), 0, s, p, count, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_keys(const uint8_t* keys, size_t key_stride, int count, const uint32_t* T0,
+                              uint32_t* rk_out, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_expand_keys, dim3(nblk(count, 64)), dim3(64), 0, s, keys, key_stride, count,
+                     T0, rk_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_keystream(const uint32_t* rk, const uint32_t* T0, uint32_t domain, uint64_t block0,
+                            size_t nblocks, uint8_t* out, hipStream_t s) {
+  if (nblocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_keystream, dim3(nblk(nblocks, 256)), dim3(256), 0, s, rk, T0, bswap32(domain),
+                     block0, nblocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_A(const Params& p, const uint32_t* rk, const uint32_t* T0, uint32_t col0,
+                           uint32_t ncols, uint16_t* out, hipStream_t s) {
+  const size_t work = (size_t)ncols * (p.n / 8);
+  if (work == 0) return hipSuccess;
+  const uint32_t qmask2 = ((1u << p.logq) - 1u) * 0x10001u;
+  hipLaunchKernelGGL(k_expand_A, dim3(nblk(work, 256)), dim3(256), 0, s, p.n, qmask2, rk, T0, col0,
+                     ncols, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_stream(const Params& p, const uint32_t* rk, const uint32_t* T0, uint32_t domain,
+                                uint64_t word0, size_t count, int16_t* out, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  SampTable st;
+  for (int k = 0; k <= MAX_K; ++k) st.T[k] = p.T[k];
+  hipLaunchKernelGGL(k_sample_stream, dim3(nblk(count, 256)), dim3(256), 0, s, st, p.K, rk, T0,
+                     bswap32(domain), word0, count, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample(const SampleArgs& a, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const int total = 2 * a.n + (a.nseg == 3 ? 8 : 0);
+  const unsigned gx = (unsigned)((total + a.chunk - 1) / a.chunk);
+  hipLaunchKernelGGL(k_sample, dim3(gx, (unsigned)count), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int CG, int RG, bool TRANS>
+static hipError_t launch_stream_t(const ProdArgs& a, int waves, int n_row_tiles, int ks, hipStream_t s) {
+  const size_t lds = 4096 + (size_t)waves * RG * CG * 256 * 4 + (TRANS ? (size_t)waves * 2 * CG * 1024 : 0);
+  hipLaunchKernelGGL((k_prod_stream<CG, RG, TRANS>), dim3((unsigned)(a.n_jt * a.n_kc), (unsigned)n_row_tiles),
+                     dim3(64 * waves), lds, s, a, ks);
+  return hipGetLastError();
+}
+
+hipError_t launch_product_stream(const ProdArgs& a, int cg, int rg, int waves, bool trans, int n_row_tiles,
+                                 int ks, hipStream_t s) {
+#define LWE_STREAM_CASE(CG_, RG_)                                                  \
+  if (cg == CG_ && rg == RG_)                                                      \
+    return trans ? launch_stream_t<CG_, RG_, true>(a, waves, n_row_tiles, ks, s)   \
+                 : launch_stream_t<CG_, RG_, false>(a, waves, n_row_tiles, ks, s);
+  LWE_STREAM_CASE(1, 1)
+  LWE_STREAM_CASE(1, 2)
+  LWE_STREAM_CASE(1, 4)
+  LWE_STREAM_CASE(2, 1)
+  LWE_STREAM_CASE(2, 2)
+  LWE_STREAM_CASE(2, 4)
+#undef LWE_STREAM_CASE
+  return hipErrorInvalidValue;
+}
+
+size_t product_strip_lds_bytes(int cg, int kc_len) {
+  const int ksteps = (kc_len + 63) / 64;
+  return 4096 + (size_t)ksteps * 64 * 16 * cg * 2;
+}
+
+template <int CG, int RG>
+static hipError_t launch_strip_t(const ProdArgs& a, hipStream_t s) {
+  const size_t lds = product_strip_lds_bytes(CG, a.kc_len);
+  const int total = a.n_jt * a.n_kc * a.n_mt;
+  const unsigned grid = (unsigned)(8 * ((total + 7) / 8));
+  hipLaunchKernelGGL((k_prod_strip<CG, RG>), dim3(grid), dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_product_strip(const ProdArgs& a, int cg, int rg, hipStream_t s) {
+#define LWE_STRIP_CASE(CG_, RG_) \
+  if (cg == CG_ && rg == RG_) return launch_strip_t<CG_, RG_>(a, s);
+  LWE_STRIP_CASE(1, 1)
+  LWE_STRIP_CASE(1, 2)
+  LWE_STRIP_CASE(1, 4)
+  LWE_STRIP_CASE(2, 1)
+  LWE_STRIP_CASE(2, 2)
+  LWE_STRIP_CASE(2, 4)
+  LWE_STRIP_CASE(4, 1)
+  LWE_STRIP_CASE(4, 2)
+#undef LWE_STRIP_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_finalize(const ProdArgs& a, hipStream_t s) {
+  const size_t total = (size_t)a.M * a.ncols;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finalize, dim3(nblk(total, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_decrypt(const DecArgs& a, hipStream_t s) {
+  if (a.count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_decrypt, dim3((unsigned)((a.count + 1) / 2)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fo_coins(int count, const uint8_t* pkh, const uint8_t* mu, size_t mu_stride, int mu_bytes,
+                           uint8_t* coins, uint8_t* kprime, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fo_coins, dim3(nblk(count, 64)), dim3(64), 0, s, count, pkh, mu, mu_stride, mu_bytes,
+                     coins, kprime);
+  return hipGetLastError();
+}
+
+hipError_t launch_hash_records(int count, const uint8_t* in, size_t stride, size_t len, uint8_t* out,
+                               hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hash_records, dim3(nblk(count, 64)), dim3(64), 0, s, count, in, stride, len, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_final_ss(int count, const uint32_t* flags, const uint8_t* kprime, const uint8_t* z,
+                           const uint8_t* hct, uint8_t* ss, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_final_ss, dim3(nblk(count, 64)), dim3(64), 0, s, count, flags, kprime, z, hct, ss);
+  return hipGetLastError();
+}
+
+template <int CG, int RG>
+static hipError_t allow_lds_strip() {
+  return hipFuncSetAttribute((const void*)k_prod_strip<CG, RG>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             160 * 1024);
+}
+template <int CG, int RG, bool TR>
+static hipError_t allow_lds_stream() {
+  return hipFuncSetAttribute((const void*)k_prod_stream<CG, RG, TR>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+hipError_t init_kernels() {
+  hipError_t e = hipSuccess, r;
+#define LWE_TRY(x) \
+  if ((r = (x)) != hipSuccess) e = r;
+  LWE_TRY((allow_lds_strip<1, 1>()))
+  LWE_TRY((allow_lds_strip<1, 2>()))
+  LWE_TRY((allow_lds_strip<1, 4>()))
+  LWE_TRY((allow_lds_strip<2, 1>()))
+  LWE_TRY((allow_lds_strip<2, 2>()))
+  LWE_TRY((allow_lds_strip<2, 4>()))
+  LWE_TRY((allow_lds_strip<4, 1>()))
+  LWE_TRY((allow_lds_strip<4, 2>()))
+  LWE_TRY((allow_lds_stream<1, 1, false>()))
+  LWE_TRY((allow_lds_stream<1, 2, false>()))
+  LWE_TRY((allow_lds_stream<1, 4, false>()))
+  LWE_TRY((allow_lds_stream<2, 1, false>()))
+  LWE_TRY((allow_lds_stream<2, 2, false>()))
+  LWE_TRY((allow_lds_stream<2, 4, false>()))
+  LWE_TRY((allow_lds_stream<1, 1, true>()))
+  LWE_TRY((allow_lds_stream<1, 2, true>()))
+  LWE_TRY((allow_lds_stream<1, 4, true>()))
+  LWE_TRY((allow_lds_stream<2, 1, true>()))
+  LWE_TRY((allow_lds_stream<2, 2, true>()))
+  LWE_TRY((allow_lds_stream<2, 4, true>()))
+#undef LWE_TRY
+  return e;
+}
+
+}  // namespace lwe

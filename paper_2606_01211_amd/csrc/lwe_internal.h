@@ -1,0 +1,104 @@
+// Internal declarations of liblwe_hip: parameter registry, kernel argument blocks and
+// kernel launchers.  Not part of the public ABI (include/lwe.h is).
+#pragma once
+
+#include "../../include/lwe.h"
+#include "lwe_common.h"
+
+namespace lwe {
+
+// ---- registry (params.cpp) ----
+bool build_cdf(int K, double sigma, uint16_t* T);
+void finish_params(Params& p);
+const Params* get_params(int pid);
+int find_param(uint32_t n);
+int register_param(uint32_t n, uint32_t logq, uint32_t B, uint32_t K, double sigma);
+const uint32_t* aes_T0();
+const uint8_t* aes_sbox();
+
+// ---- kernel argument blocks (kernels.hip) ----
+enum ProdMode : int { PM_KEYGEN = 0, PM_ENCRYPT = 1, PM_COMPARE = 2 };
+
+// Product D = X * Y over the contraction index k, where X is an int8 matrix with M rows
+// (S^T stacks for keygen, S' stacks for encryption) and Y is A (encryption) or A^T
+// (keygen) regenerated from AES-128-CTR, extended for encryption by the 8 columns of
+// B = (B^T)^T so that V = S' B is computed by the same contraction.
+struct ProdArgs {
+  const uint32_t* rkA;   // round keys of seedA: 44 words, or [inst][44] if per_inst_A
+  const uint32_t* T0;    // AES T-table (256 words, global)
+  const int8_t* X;       // [M][ldx] int8, zero padded beyond n
+  int ldx;
+  int M;                 // valid rows (8 per instance)
+  int n, logq, B;
+  int ncols;             // n (keygen) or n + 8 (encryption: A | B)
+  const uint8_t* Bt;     // encryption: B^T (8 x n uint16) of the shared public key
+  int kc_len;            // contraction rows per K chunk (multiple of 64)
+  int n_kc;              // number of K chunks; > 1 accumulates partials into acc32
+  int n_jt;              // column tiles
+  int m_tile;            // rows per row tile (multiple of 16)
+  int n_mt;              // row tiles
+  int per_inst_A;        // keygen batches: every instance has its own A (row tile = instance)
+  int32_t* acc32;        // split-K accumulator [M][acc_ld], zeroed before the launch
+  int acc_ld;
+  int mode;              // ProdMode
+  const int8_t* E;       // keygen E^T / encryption E': [M][n] int8
+  const int8_t* E2;      // encryption E'': [count][64] int8
+  const uint8_t* mu;     // encryption messages [count][mu_stride]
+  size_t mu_stride;
+  uint8_t* out;          // keygen: pk records, encryption: ct records
+  size_t out_stride, out_off;
+  const uint8_t* cmp;    // compare: received ct records
+  size_t cmp_stride;
+  uint32_t* flags;       // compare: per instance, nonzero if any coefficient differs
+};
+
+struct SampleArgs {
+  const uint32_t* rk;    // [count][44]
+  const uint32_t* T0;
+  int n, K, ldx;
+  int nseg;              // 2 (keygen: S^T, E^T) or 3 (encryption: S', E', E'')
+  uint16_t T[MAX_K + 1];
+  int8_t* X;             // segment 0 (domain 1): [count*8][ldx]
+  uint8_t* X16;          // optional int16 copy of segment 0 (secret key bytes), may be null
+  size_t x16_stride;
+  int8_t* E;             // segment 1 (domain 2): [count*8][n]
+  int8_t* E2;            // segment 2 (domain 3): [count][64]
+  int chunk;             // AES blocks per workgroup
+};
+
+struct DecArgs {
+  const uint8_t* ct;     // [count][ct_stride]
+  size_t ct_stride;
+  const uint8_t* St16;   // S^T int16 (8 x n), shared
+  int n, logq, B, count;
+  int mu_bytes;
+  uint8_t* mu_out;       // [count][mu_bytes]
+};
+
+// ---- launchers (kernels.hip); all return hipError_t of the launch ----
+hipError_t launch_fill_u32(uint32_t* p, size_t count, uint32_t v, hipStream_t s);
+hipError_t launch_expand_keys(const uint8_t* keys, size_t key_stride, int count,
+                              const uint32_t* T0, uint32_t* rk_out, hipStream_t s);
+hipError_t launch_keystream(const uint32_t* rk, const uint32_t* T0, uint32_t domain,
+                            uint64_t block0, size_t nblocks, uint8_t* out, hipStream_t s);
+hipError_t launch_expand_A(const Params& p, const uint32_t* rk, const uint32_t* T0,
+                           uint32_t col0, uint32_t ncols, uint16_t* out, hipStream_t s);
+hipError_t launch_sample_stream(const Params& p, const uint32_t* rk, const uint32_t* T0,
+                                uint32_t domain, uint64_t word0, size_t count, int16_t* out,
+                                hipStream_t s);
+hipError_t launch_sample(const SampleArgs& a, int count, hipStream_t s);
+hipError_t launch_product_stream(const ProdArgs& a, int cg, int rg, int waves, bool trans,
+                                 int n_row_tiles, int ksteps_per_wave, hipStream_t s);
+hipError_t launch_product_strip(const ProdArgs& a, int cg, int rg, hipStream_t s);
+size_t product_strip_lds_bytes(int cg, int kc_len);
+hipError_t launch_finalize(const ProdArgs& a, hipStream_t s);
+hipError_t launch_decrypt(const DecArgs& a, hipStream_t s);
+hipError_t launch_fo_coins(int count, const uint8_t* pkh, const uint8_t* mu, size_t mu_stride,
+                           int mu_bytes, uint8_t* coins, uint8_t* kprime, hipStream_t s);
+hipError_t launch_hash_records(int count, const uint8_t* in, size_t stride, size_t len,
+                               uint8_t* out, hipStream_t s);
+hipError_t launch_final_ss(int count, const uint32_t* flags, const uint8_t* kprime,
+                           const uint8_t* z, const uint8_t* hct, uint8_t* ss, hipStream_t s);
+hipError_t init_kernels();
+
+}  // namespace lwe

@@ -1,0 +1,295 @@
+"""GPU parity: every stage of the HIP path against the CPU oracle, bit-exact (tolerance 0:
+all arithmetic is integer).  Calls go through the C ABI (liblwe_hip.so via ctypes).
+
+Sizes: the registry sets n = 640 (q = 2^15), 976 (ragged contraction tail: 976 = 15*64 + 16),
+1344, a custom n = 200 (n = 8 mod 16: half-filled fragments), 8192 in full and 32768 at
+sampled outputs; batch sizes cross the host/device hashing threshold (16) and the
+streaming/strip product threshold (32 instances)."""
+import hashlib
+import sys
+
+import numpy as np
+import pytest
+
+import lwe_inputs
+
+pytestmark = pytest.mark.gpu
+H = lambda b: hashlib.sha3_256(b).digest()  # noqa: E731
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def L():
+    import paper_2606_01211_amd as mod
+
+    return mod
+
+
+def _pair(orc, n):
+    """(library params, oracle params) for registry n or the custom n = 200 set."""
+    lib = L()
+    if n == 200:
+        pid = lib.register_params(200, 16, 2, 6, 1.4)
+        return lib.params(pid), orc.Params(200, 16, 2, 6, 1.4)
+    return lib.params(lib.param_id(n)), orc.params_for(n)
+
+
+def test_keystream(ctx, orc):
+    g = lwe_inputs.rng(0, 1000)
+    for domain, block0, nb in [(0, 0, 4096), (1, 7, 333), (3, 2**32 - 5, 64), (2, 2**40 + 3, 17)]:
+        say("keystream", domain, block0, nb)
+        key = lwe_inputs.random_bytes(g, 1, 16)[0].tobytes()
+        out = np.zeros(16 * nb, np.uint8)
+        ctx.test_keystream(key, domain, block0, nb, out)
+        assert out.tobytes() == orc.ctr_blocks(key, domain, block0, nb)
+
+
+@pytest.mark.parametrize("n", [200, 640, 976, 1344])
+def test_expand_A_full(ctx, orc, n):
+    lp, op = _pair(orc, n)
+    seedA = lwe_inputs.random_bytes(lwe_inputs.rng(0, 1100 + n), 1, 16)[0].tobytes()
+    say("expand_A", n)
+    out = np.zeros((n, n), np.uint16)
+    ctx.test_expand_A(lp.pid, seedA, 0, n, out)
+    assert np.array_equal(out, orc.expand_A_cols(op, seedA, 0, n))
+
+
+def test_expand_A_sampled_32768(ctx, orc):
+    lp, op = _pair(orc, 32768)
+    seedA = bytes(range(3, 19))
+    for col0, nc in [(0, 2), (16383, 3), (32766, 2)]:
+        say("expand_A 32768", col0, nc)
+        out = np.zeros((nc, 32768), np.uint16)
+        ctx.test_expand_A(lp.pid, seedA, col0, nc, out)
+        assert np.array_equal(out, orc.expand_A_cols(op, seedA, col0, nc))
+
+
+@pytest.mark.parametrize("n", [200, 640, 976, 1344])
+def test_sampler(ctx, orc, n):
+    lp, op = _pair(orc, n)
+    key = lwe_inputs.random_bytes(lwe_inputs.rng(0, 1200 + n), 1, 16)[0].tobytes()
+    for domain, word0, cnt in [(1, 0, 8 * n), (2, 5, 3001), (3, 0, 64)]:
+        say("sample", n, domain, word0, cnt)
+        out = np.zeros(cnt, np.int16)
+        ctx.test_sample(lp.pid, key, domain, word0, cnt, out)
+        assert np.array_equal(out, orc.sample_stream(op, key, domain, word0, cnt))
+
+
+@pytest.mark.parametrize("length", [0, 1, 135, 136, 137, 1000, 21632])
+def test_device_sha3(ctx, length):
+    g = lwe_inputs.rng(0, 1300 + length)
+    cnt = 5
+    data = lwe_inputs.random_bytes(g, cnt, max(1, length))[:, :length].copy()
+    out = np.zeros((cnt, 32), np.uint8)
+    say("sha3", length)
+    ctx.test_sha3(cnt, length, data, out)
+    for i in range(cnt):
+        assert out[i].tobytes() == H(data[i].tobytes())
+
+
+def _keypair(orc, op, g):
+    seedA, seedSK, z = lwe_inputs.keygen_seeds(g, 1)
+    pk, sk = orc.kem_keygen(op, seedA[0].tobytes(), seedSK[0].tobytes(), z[0].tobytes())
+    return pk, sk
+
+
+@pytest.mark.parametrize("n", [200, 640, 976, 1344])
+@pytest.mark.parametrize("count", [1, 3, 40, 300])
+def test_encrypt(ctx, orc, n, count):
+    """B' = S'A + E' and V = S'B + E'' + enc(mu) (Alg. 2) for explicit coins; count 300 takes
+    the strip (batched) product kernel, smaller counts the streaming one."""
+    lp, op = _pair(orc, n)
+    g = lwe_inputs.rng(0, 1400 + n + count)
+    pk, _ = _keypair(orc, op, g)
+    coins = lwe_inputs.coins(g, count)
+    mus = lwe_inputs.messages(g, count, op.mu_bytes)
+    say("encrypt", n, count)
+    ct = np.zeros((count, op.ct_bytes), np.uint8)
+    ctx.test_encrypt(lp.pid, count, pk, coins, mus, ct)
+    Bt = np.frombuffer(pk[16:], "<u2").reshape(8, n)
+    for i in sorted(set([0, count - 1, count // 2, count // 3])):
+        Bp, V = orc.pke_encrypt(op, pk[:16], Bt, coins[i].tobytes(), mus[i].tobytes())
+        assert ct[i].tobytes() == Bp.astype("<u2").tobytes() + V.astype("<u2").tobytes(), i
+
+
+@pytest.mark.parametrize("n", [200, 640, 976, 1344])
+def test_decrypt(ctx, orc, n):
+    lp, op = _pair(orc, n)
+    g = lwe_inputs.rng(0, 1500 + n)
+    pk, sk = _keypair(orc, op, g)
+    count = 7
+    mus = lwe_inputs.messages(g, count, op.mu_bytes)
+    cts = np.stack([np.frombuffer(orc.kem_encaps(op, pk, mus[i].tobytes())[0], np.uint8) for i in range(count)])
+    out = np.zeros((count, op.mu_bytes), np.uint8)
+    say("decrypt", n)
+    ctx.test_decrypt(lp.pid, count, sk, cts, out)
+    assert np.array_equal(out, mus)
+
+
+@pytest.mark.parametrize("n", [200, 640, 976, 1344])
+@pytest.mark.parametrize("count", [1, 4])
+def test_keygen(ctx, orc, n, count):
+    lp, op = _pair(orc, n)
+    g = lwe_inputs.rng(0, 1600 + n + count)
+    seedA, seedSK, z = lwe_inputs.keygen_seeds(g, count)
+    pk = np.zeros((count, op.pk_bytes), np.uint8)
+    sk = np.zeros((count, op.sk_bytes), np.uint8)
+    say("keygen", n, count)
+    ctx.keygen_batch(lp.pid, count, seedA, seedSK, z, pk, sk)
+    for i in range(count):
+        opk, osk = orc.kem_keygen(op, seedA[i].tobytes(), seedSK[i].tobytes(), z[i].tobytes())
+        assert pk[i].tobytes() == opk, i
+        assert sk[i].tobytes() == osk, i
+
+
+@pytest.mark.parametrize("n", [200, 640, 976, 1344])
+@pytest.mark.parametrize("count", [1, 20, 300])
+def test_encaps_decaps(ctx, orc, n, count):
+    """Encaps (Alg. 4) and Decaps (Alg. 5) against the oracle; a quarter of the ciphertexts
+    are tampered before decapsulation (implicit rejection)."""
+    lp, op = _pair(orc, n)
+    g = lwe_inputs.rng(0, 1700 + n + count)
+    pk, sk = _keypair(orc, op, g)
+    mus = lwe_inputs.messages(g, count, op.mu_bytes)
+    ct = np.zeros((count, op.ct_bytes), np.uint8)
+    ss = np.zeros((count, 32), np.uint8)
+    say("encaps", n, count)
+    ctx.encaps_batch(lp.pid, count, pk, mus, ct, ss)
+    check = sorted(set([0, count - 1, count // 2, count // 5]))
+    for i in check:
+        oct_, oss = orc.kem_encaps(op, pk, mus[i].tobytes())
+        assert ct[i].tobytes() == oct_, i
+        assert ss[i].tobytes() == oss, i
+    bad = ct.copy()
+    tampered = list(range(0, count, 4))
+    for i in tampered:
+        bad[i, (i * 97) % op.ct_bytes] ^= 1 << (i % 8)
+    ss2 = np.zeros((count, 32), np.uint8)
+    say("decaps", n, count)
+    ctx.decaps_batch(lp.pid, count, sk, bad, ss2)
+    for i in range(count):
+        if i in tampered:
+            if i in check or i < 8:
+                oss, ok = orc.kem_decaps(op, sk, bad[i].tobytes())
+                assert not ok
+                assert ss2[i].tobytes() == oss, i
+        else:
+            assert ss2[i].tobytes() == ss[i].tobytes(), i
+
+
+def test_device_tensors_async(ctx, orc):
+    """Device-resident buffers on a torch stream: the same bytes as the host path."""
+    import torch
+
+    lp, op = _pair(orc, 1344)
+    g = lwe_inputs.rng(0, 1800)
+    pk, sk = _keypair(orc, op, g)
+    count = 64
+    mus = lwe_inputs.messages(g, count, op.mu_bytes)
+    dev = torch.device("cuda:0")
+    d_pk = torch.from_numpy(np.frombuffer(pk, np.uint8).copy()).to(dev)
+    d_sk = torch.from_numpy(np.frombuffer(sk, np.uint8).copy()).to(dev)
+    d_mu = torch.from_numpy(mus).to(dev)
+    d_ct = torch.empty((count, op.ct_bytes), dtype=torch.uint8, device=dev)
+    d_ss = torch.empty((count, 32), dtype=torch.uint8, device=dev)
+    d_ss2 = torch.empty((count, 32), dtype=torch.uint8, device=dev)
+    say("device tensors encaps/decaps")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ctx.encaps_batch(lp.pid, count, d_pk, d_mu, d_ct, d_ss)
+        ctx.decaps_batch(lp.pid, count, d_sk, d_ct, d_ss2)
+    s.synchronize()
+    ct = d_ct.cpu().numpy()
+    ss = d_ss.cpu().numpy()
+    assert np.array_equal(ss, d_ss2.cpu().numpy())
+    for i in [0, 31, 63]:
+        oct_, oss = orc.kem_encaps(op, pk, mus[i].tobytes())
+        assert ct[i].tobytes() == oct_ and ss[i].tobytes() == oss
+
+
+def test_batch_equals_single(ctx, orc):
+    """Instance i of a batch is byte-identical to the same instance run alone."""
+    lp, op = _pair(orc, 1344)
+    g = lwe_inputs.rng(0, 1900)
+    pk, sk = _keypair(orc, op, g)
+    count = 257
+    mus = lwe_inputs.messages(g, count, op.mu_bytes)
+    ct = np.zeros((count, op.ct_bytes), np.uint8)
+    ss = np.zeros((count, 32), np.uint8)
+    say("batch vs single")
+    ctx.encaps_batch(lp.pid, count, pk, mus, ct, ss)
+    for i in [0, 100, 256]:
+        c1 = np.zeros(op.ct_bytes, np.uint8)
+        s1 = np.zeros(32, np.uint8)
+        ctx.encaps(lp.pid, pk, mus[i], c1, s1)
+        assert np.array_equal(c1, ct[i]) and np.array_equal(s1, ss[i])
+
+
+@pytest.mark.parametrize("n", [8192])
+def test_large_n_full(ctx, orc, n):
+    lp, op = _pair(orc, n)
+    g = lwe_inputs.rng(2, n)
+    seedA, seedSK, z = lwe_inputs.keygen_seeds(g, 1)
+    pk = np.zeros(op.pk_bytes, np.uint8)
+    sk = np.zeros(op.sk_bytes, np.uint8)
+    say("large keygen", n)
+    ctx.keygen(lp.pid, seedA[0], seedSK[0], z[0], pk, sk)
+    opk, osk = orc.kem_keygen(op, seedA[0].tobytes(), seedSK[0].tobytes(), z[0].tobytes())
+    assert pk.tobytes() == opk and sk.tobytes() == osk
+    mu = lwe_inputs.messages(g, 1, op.mu_bytes)[0]
+    ct = np.zeros(op.ct_bytes, np.uint8)
+    ss = np.zeros(32, np.uint8)
+    say("large encaps", n)
+    ctx.encaps(lp.pid, pk, mu, ct, ss)
+    oct_, oss = orc.kem_encaps(op, opk, mu.tobytes())
+    assert ct.tobytes() == oct_ and ss.tobytes() == oss
+    ss2 = np.zeros(32, np.uint8)
+    say("large decaps", n)
+    ctx.decaps(lp.pid, sk, ct, ss2)
+    assert np.array_equal(ss2, ss)
+
+
+@pytest.mark.parametrize("n", [16384, 32768])
+def test_large_n_sampled(ctx, orc, n):
+    """At n = 16384 and 32768 the oracle checks sampled entries of B^T and B', all of V, the
+    hashes, and the KEM invariant."""
+    lp, op = _pair(orc, n)
+    g = lwe_inputs.rng(2, n)
+    seedA, seedSK, z = lwe_inputs.keygen_seeds(g, 1)
+    sA, sS, zz = seedA[0].tobytes(), seedSK[0].tobytes(), z[0].tobytes()
+    pk = np.zeros(op.pk_bytes, np.uint8)
+    sk = np.zeros(op.sk_bytes, np.uint8)
+    say("sampled keygen", n)
+    ctx.keygen(lp.pid, seedA[0], seedSK[0], z[0], pk, sk)
+    Bt = np.frombuffer(pk.tobytes()[16:], "<u2").reshape(8, n)
+    assert pk.tobytes()[:16] == sA
+    for c, i in [(0, 0), (7, n - 1), (3, n // 2 + 5), (5, 12345 % n)]:
+        assert Bt[c, i] == orc.Bt_entry(op, sA, sS, c, i), (c, i)
+    St = np.frombuffer(sk.tobytes()[:16 * n], "<i2").reshape(8, n)
+    assert np.array_equal(St.reshape(-1), orc.sample_stream(op, sS, 1, 0, 8 * n))
+    skb = sk.tobytes()
+    assert skb[16 * n:16 * n + op.pk_bytes] == pk.tobytes()
+    assert skb[16 * n + op.pk_bytes:16 * n + op.pk_bytes + 32] == H(pk.tobytes()) and skb[-32:] == zz
+    mu = lwe_inputs.messages(g, 1, op.mu_bytes)[0]
+    ct = np.zeros(op.ct_bytes, np.uint8)
+    ss = np.zeros(32, np.uint8)
+    say("sampled encaps", n)
+    ctx.encaps(lp.pid, pk, mu, ct, ss)
+    coins, kp = orc.fo_coins(op, H(pk.tobytes()), mu.tobytes())
+    Bp = np.frombuffer(ct.tobytes()[:16 * n], "<u2").reshape(8, n)
+    for r, j in [(0, 0), (7, n - 1), (2, n // 3), (6, 9999 % n)]:
+        assert Bp[r, j] == orc.Bp_entry(op, sA, coins, r, j), (r, j)
+    V = np.frombuffer(ct.tobytes()[16 * n:], "<u2").reshape(8, 8)
+    assert np.array_equal(V, orc.pke_V(op, Bt, coins, mu.tobytes()))
+    assert ss.tobytes() == H(kp + H(ct.tobytes()))
+    ss2 = np.zeros(32, np.uint8)
+    say("sampled decaps", n)
+    ctx.decaps(lp.pid, sk, ct, ss2)
+    assert np.array_equal(ss, ss2)
+    bad = ct.copy()
+    bad[5] ^= 4
+    ctx.decaps(lp.pid, sk, bad, ss2)
+    assert ss2.tobytes() == H(zz + H(bad.tobytes()))
