@@ -143,6 +143,16 @@ int lwe_test_decrypt(lwe_ctx* ctx, int pid, size_t count, const uint8_t* sk, con
 int lwe_test_sha3(lwe_ctx* ctx, size_t count, size_t len, const uint8_t* in, uint8_t* out,
                   void* hip_stream);
 
+/* Kernel timing for measurement.  While enabled, every kernel the context launches is
+ * bracketed by a pair of HIP events on the stream it runs on.  lwe_prof_read synchronises
+ * the recorded events and returns, for one kernel name ("sample", "prod_strip",
+ * "prod_stream", "finalize", "decrypt", "fo_coins", "expand_keys", "hash_records",
+ * "final_ss", "fill", "keystream", "sample_stream"), the number of launches and their
+ * summed device time since the last reset. */
+int lwe_prof_enable(lwe_ctx* ctx, int on);
+int lwe_prof_reset(lwe_ctx* ctx);
+int lwe_prof_read(lwe_ctx* ctx, const char* kernel, uint64_t* launches, double* total_ms);
+
 /* Tuning knobs of the batched product kernel (see lwe_tune_* in the Python package).
  * Zero leaves a knob at its built-in default. */
 typedef struct {

@@ -3,6 +3,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -39,6 +41,15 @@ struct lwe_ctx {
   uint8_t pkh_cache[32];
   lwe_tuning tuning[256];
   int host_threads = 1;
+  // kernel timing (lwe_prof_*): events bracketing each launch, resolved lazily
+  struct ProfRec {
+    const char* name;
+    hipEvent_t a, b;
+  };
+  bool prof_on = false;
+  std::vector<ProfRec> prof_pending;
+  std::vector<hipEvent_t> prof_pool;
+  std::map<std::string, std::pair<uint64_t, double>> prof_agg;
 };
 
 namespace {
@@ -168,6 +179,56 @@ int finish_out(const OutStage& o, hipStream_t s) {
 
 hipStream_t pick_stream(lwe_ctx* c, void* user) { return user ? (hipStream_t)user : c->own; }
 
+hipEvent_t prof_event(lwe_ctx* c) {
+  if (!c->prof_pool.empty()) {
+    hipEvent_t e = c->prof_pool.back();
+    c->prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one kernel launch with events when profiling is on.
+struct ProfScope {
+  lwe_ctx* c;
+  const char* name;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  ProfScope(lwe_ctx* c_, const char* n, hipStream_t s_) : c(c_), name(n), s(s_) {
+    if (c->prof_on && (a = prof_event(c)) != nullptr) (void)hipEventRecord(a, s);
+  }
+  ~ProfScope() {
+    if (!a) return;
+    hipEvent_t b = prof_event(c);
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    c->prof_pending.push_back({name, a, b});
+  }
+};
+
+int prof_resolve(lwe_ctx* c) {
+  for (auto& r : c->prof_pending) {
+    if (hipEventSynchronize(r.b) != hipSuccess) return LWE_EDEVICE;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return LWE_EDEVICE;
+    auto& agg = c->prof_agg[r.name];
+    agg.first += 1;
+    agg.second += ms;
+    c->prof_pool.push_back(r.a);
+    c->prof_pool.push_back(r.b);
+  }
+  c->prof_pending.clear();
+  return LWE_OK;
+}
+
+#define KLAUNCH(name, s, x)          \
+  do {                               \
+    ProfScope ps_(c, name, s);       \
+    HIP_CHECK(x);                    \
+  } while (0)
+
 // Parallel loop over [0, count) on host threads (used for host-side hashing).
 template <class F>
 void host_for(int threads, size_t count, F f) {
@@ -217,9 +278,9 @@ int run_product(lwe_ctx* c, int pid, const Params& p, ProdArgs a, bool trans, hi
     if (a.n_kc > 1) {
       a.acc_ld = a.ncols;
       LWE_CHECK(ensure_t(c, B_ACC, (size_t)a.M * a.acc_ld * 4, &a.acc32));
-      HIP_CHECK(launch_fill_u32((uint32_t*)a.acc32, (size_t)a.M * a.acc_ld, 0, s));
+      KLAUNCH("fill", s, launch_fill_u32((uint32_t*)a.acc32, (size_t)a.M * a.acc_ld, 0, s));
     }
-    HIP_CHECK(launch_product_stream(a, CG, RG, W, trans, a.n_mt, KS, s));
+    KLAUNCH("prod_stream", s, launch_product_stream(a, CG, RG, W, trans, a.n_mt, KS, s));
   } else {
     int CG = tu.col_groups ? (int)tu.col_groups : 2;
     int RG = tu.row_groups ? (int)tu.row_groups : 4;
@@ -236,11 +297,11 @@ int run_product(lwe_ctx* c, int pid, const Params& p, ProdArgs a, bool trans, hi
     if (a.n_kc > 1) {
       a.acc_ld = a.ncols;
       LWE_CHECK(ensure_t(c, B_ACC, (size_t)a.M * a.acc_ld * 4, &a.acc32));
-      HIP_CHECK(launch_fill_u32((uint32_t*)a.acc32, (size_t)a.M * a.acc_ld, 0, s));
+      KLAUNCH("fill", s, launch_fill_u32((uint32_t*)a.acc32, (size_t)a.M * a.acc_ld, 0, s));
     }
-    HIP_CHECK(launch_product_strip(a, CG, RG, s));
+    KLAUNCH("prod_strip", s, launch_product_strip(a, CG, RG, s));
   }
-  if (a.n_kc > 1) HIP_CHECK(launch_finalize(a, s));
+  if (a.n_kc > 1) KLAUNCH("finalize", s, launch_finalize(a, s));
   return LWE_OK;
 }
 
@@ -260,7 +321,7 @@ int encrypt_core(lwe_ctx* c, int pid, const Params& p, size_t count, const uint8
   LWE_CHECK(ensure_t(c, B_E, count * 8 * (size_t)n, &E));
   LWE_CHECK(ensure_t(c, B_E2, count * 64, &E2));
   LWE_CHECK(ensure_t(c, B_RKA, 44 * 4, &rkA));
-  HIP_CHECK(launch_expand_keys(pk_dev, 0, 1, c->d_T0, rkA, s));
+  KLAUNCH("expand_keys", s, launch_expand_keys(pk_dev, 0, 1, c->d_T0, rkA, s));
   SampleArgs sa;
   memset(&sa, 0, sizeof(sa));
   sa.rk = d_rk;
@@ -274,7 +335,7 @@ int encrypt_core(lwe_ctx* c, int pid, const Params& p, size_t count, const uint8
   sa.E = E;
   sa.E2 = E2;
   sa.chunk = 2048;
-  HIP_CHECK(launch_sample(sa, (int)count, s));
+  KLAUNCH("sample", s, launch_sample(sa, (int)count, s));
   ProdArgs a;
   memset(&a, 0, sizeof(a));
   a.rkA = rkA;
@@ -370,11 +431,42 @@ void lwe_ctx_destroy(lwe_ctx* c) {
   for (auto& b : c->bufs)
     if (b.p) (void)hipFree(b.p);
   if (c->d_T0) (void)hipFree(c->d_T0);
+  for (auto& r : c->prof_pending) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : c->prof_pool) (void)hipEventDestroy(e);
   if (c->own) (void)hipStreamDestroy(c->own);
   delete c;
 }
 
 size_t lwe_ctx_device_bytes(const lwe_ctx* c) { return c ? c->held + 1024 : 0; }
+
+int lwe_prof_enable(lwe_ctx* c, int on) {
+  if (!c) return LWE_EINVAL;
+  DevGuard g(c->device);
+  LWE_CHECK(prof_resolve(c));
+  c->prof_on = on != 0;
+  return LWE_OK;
+}
+
+int lwe_prof_reset(lwe_ctx* c) {
+  if (!c) return LWE_EINVAL;
+  DevGuard g(c->device);
+  LWE_CHECK(prof_resolve(c));
+  c->prof_agg.clear();
+  return LWE_OK;
+}
+
+int lwe_prof_read(lwe_ctx* c, const char* kernel, uint64_t* launches, double* total_ms) {
+  if (!c || !kernel || !launches || !total_ms) return LWE_EINVAL;
+  DevGuard g(c->device);
+  LWE_CHECK(prof_resolve(c));
+  auto it = c->prof_agg.find(kernel);
+  *launches = it == c->prof_agg.end() ? 0 : it->second.first;
+  *total_ms = it == c->prof_agg.end() ? 0.0 : it->second.second;
+  return LWE_OK;
+}
 
 int lwe_param_id(uint32_t n) { return find_param(n); }
 
@@ -463,8 +555,8 @@ int lwe_keygen_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* seedA, co
   LWE_CHECK(ensure_t(c, B_RK, count * 44 * 4, &rkS));
   LWE_CHECK(ensure_t(c, B_X, count * 8 * (size_t)p.ldx, &X));
   LWE_CHECK(ensure_t(c, B_E, count * 8 * (size_t)n, &E));
-  HIP_CHECK(launch_expand_keys(dA, 16, (int)count, c->d_T0, rkA, s));
-  HIP_CHECK(launch_expand_keys(dS, 16, (int)count, c->d_T0, rkS, s));
+  KLAUNCH("expand_keys", s, launch_expand_keys(dA, 16, (int)count, c->d_T0, rkA, s));
+  KLAUNCH("expand_keys", s, launch_expand_keys(dS, 16, (int)count, c->d_T0, rkS, s));
   SampleArgs sa;
   memset(&sa, 0, sizeof(sa));
   sa.rk = rkS;
@@ -479,7 +571,7 @@ int lwe_keygen_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* seedA, co
   sa.x16_stride = p.sk_bytes;
   sa.E = E;
   sa.chunk = 2048;
-  HIP_CHECK(launch_sample(sa, (int)count, s));
+  KLAUNCH("sample", s, launch_sample(sa, (int)count, s));
   ProdArgs a;
   memset(&a, 0, sizeof(a));
   a.rkA = rkA;
@@ -518,7 +610,7 @@ int lwe_keygen_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* seedA, co
   } else {
     uint8_t* dh;
     LWE_CHECK(ensure_t(c, B_HCT, count * 32, &dh));
-    HIP_CHECK(launch_hash_records((int)count, opk.dev, p.pk_bytes, p.pk_bytes, dh, s));
+    KLAUNCH("hash_records", s, launch_hash_records((int)count, opk.dev, p.pk_bytes, p.pk_bytes, dh, s));
     HIP_CHECK(hipMemcpy2DAsync(osk.dev + off_pkh, p.sk_bytes, dh, 32, 32, count, hipMemcpyDeviceToDevice, s));
   }
   LWE_CHECK(finish_out(opk, s));
@@ -581,9 +673,9 @@ int lwe_encaps_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* pk, const
     uint8_t* dpkh;
     LWE_CHECK(ensure_t(c, B_PKH, 32, &dpkh));
     HIP_CHECK(hipMemcpyAsync(dpkh, pkh, 32, hipMemcpyHostToDevice, s));
-    HIP_CHECK(launch_fo_coins((int)count, dpkh, dmu, mb, (int)mb, dcoins, dkp, s));
+    KLAUNCH("fo_coins", s, launch_fo_coins((int)count, dpkh, dmu, mb, (int)mb, dcoins, dkp, s));
   }
-  HIP_CHECK(launch_expand_keys(dcoins, 16, (int)count, c->d_T0, drk, s));
+  KLAUNCH("expand_keys", s, launch_expand_keys(dcoins, 16, (int)count, c->d_T0, drk, s));
   LWE_CHECK(encrypt_core(c, pid, p, count, dpk, drk, dmu, mb, oct.dev, nullptr, nullptr, s));
   if (hh) {
     std::vector<uint8_t> hct(count * p.ct_bytes), hss(count * 32);
@@ -604,8 +696,8 @@ int lwe_encaps_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* pk, const
   } else {
     uint8_t* dhct;
     LWE_CHECK(ensure_t(c, B_HCT, count * 32, &dhct));
-    HIP_CHECK(launch_hash_records((int)count, oct.dev, p.ct_bytes, p.ct_bytes, dhct, s));
-    HIP_CHECK(launch_final_ss((int)count, nullptr, dkp, nullptr, dhct, oss.dev, s));
+    KLAUNCH("hash_records", s, launch_hash_records((int)count, oct.dev, p.ct_bytes, p.ct_bytes, dhct, s));
+    KLAUNCH("final_ss", s, launch_final_ss((int)count, nullptr, dkp, nullptr, dhct, oss.dev, s));
   }
   LWE_CHECK(finish_out(oct, s));
   LWE_CHECK(finish_out(oss, s));
@@ -658,7 +750,7 @@ int lwe_decaps_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* sk, const
   da.count = (int)count;
   da.mu_bytes = (int)mb;
   da.mu_out = dmu2;
-  HIP_CHECK(launch_decrypt(da, s));
+  KLAUNCH("decrypt", s, launch_decrypt(da, s));
   const bool hh = use_host_hash(c, pid, count);
   std::vector<uint8_t> hsk_tail, hkp, hct, hhct;
   if (hh) {
@@ -678,8 +770,8 @@ int lwe_decaps_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* sk, const
       sha3_256_3(pkh, 32, hmu.data() + i * mb, mb, nullptr, 0, hkp.data() + i * 32);
     });
     HIP_CHECK(hipMemcpyAsync(dcoins, hcoins.data(), count * 16, hipMemcpyHostToDevice, s));
-    HIP_CHECK(launch_expand_keys(dcoins, 16, (int)count, c->d_T0, drk, s));
-    HIP_CHECK(launch_fill_u32(dflags, count, 0, s));
+    KLAUNCH("expand_keys", s, launch_expand_keys(dcoins, 16, (int)count, c->d_T0, drk, s));
+    KLAUNCH("fill", s, launch_fill_u32(dflags, count, 0, s));
     LWE_CHECK(encrypt_core(c, pid, p, count, dsk + off_pk, drk, dmu2, mb, nullptr, dct, dflags, s));
     std::vector<uint32_t> hflags(count);
     HIP_CHECK(hipMemcpyAsync(hflags.data(), dflags, count * 4, hipMemcpyDeviceToHost, s));
@@ -707,14 +799,14 @@ int lwe_decaps_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* sk, const
       HIP_CHECK(hipStreamSynchronize(s));
     }
   } else {
-    HIP_CHECK(launch_fo_coins((int)count, dsk + off_pkh, dmu2, mb, (int)mb, dcoins, dkp, s));
-    HIP_CHECK(launch_expand_keys(dcoins, 16, (int)count, c->d_T0, drk, s));
-    HIP_CHECK(launch_fill_u32(dflags, count, 0, s));
+    KLAUNCH("fo_coins", s, launch_fo_coins((int)count, dsk + off_pkh, dmu2, mb, (int)mb, dcoins, dkp, s));
+    KLAUNCH("expand_keys", s, launch_expand_keys(dcoins, 16, (int)count, c->d_T0, drk, s));
+    KLAUNCH("fill", s, launch_fill_u32(dflags, count, 0, s));
     LWE_CHECK(encrypt_core(c, pid, p, count, dsk + off_pk, drk, dmu2, mb, nullptr, dct, dflags, s));
     uint8_t* dhct;
     LWE_CHECK(ensure_t(c, B_HCT, count * 32, &dhct));
-    HIP_CHECK(launch_hash_records((int)count, dct, p.ct_bytes, p.ct_bytes, dhct, s));
-    HIP_CHECK(launch_final_ss((int)count, dflags, dkp, dsk + off_z, dhct, oss.dev, s));
+    KLAUNCH("hash_records", s, launch_hash_records((int)count, dct, p.ct_bytes, p.ct_bytes, dhct, s));
+    KLAUNCH("final_ss", s, launch_final_ss((int)count, dflags, dkp, dsk + off_z, dhct, oss.dev, s));
   }
   LWE_CHECK(finish_out(oss, s));
   if (oss.host || !stream) HIP_CHECK(hipStreamSynchronize(s));
@@ -741,7 +833,7 @@ int lwe_test_expand_A(lwe_ctx* c, int pid, const uint8_t* seedA, uint32_t col0, 
   LWE_CHECK(stage_in(c, B_SEEDA, seedA, 16, s, &dA));
   uint32_t* rk;
   LWE_CHECK(ensure_t(c, B_RKA, 44 * 4, &rk));
-  HIP_CHECK(launch_expand_keys(dA, 16, 1, c->d_T0, rk, s));
+  KLAUNCH("expand_keys", s, launch_expand_keys(dA, 16, 1, c->d_T0, rk, s));
   OutStage o;
   LWE_CHECK(stage_out(c, B_TEST, out, (size_t)ncols * p.n * 2, o));
   HIP_CHECK(launch_expand_A(p, rk, c->d_T0, col0, ncols, (uint16_t*)o.dev, s));
@@ -759,10 +851,10 @@ int lwe_test_keystream(lwe_ctx* c, const uint8_t* key, uint32_t domain, uint64_t
   LWE_CHECK(stage_in(c, B_SEEDA, key, 16, s, &dk));
   uint32_t* rk;
   LWE_CHECK(ensure_t(c, B_RKA, 44 * 4, &rk));
-  HIP_CHECK(launch_expand_keys(dk, 16, 1, c->d_T0, rk, s));
+  KLAUNCH("expand_keys", s, launch_expand_keys(dk, 16, 1, c->d_T0, rk, s));
   OutStage o;
   LWE_CHECK(stage_out(c, B_TEST, out, nblocks * 16, o));
-  HIP_CHECK(launch_keystream(rk, c->d_T0, domain, block0, nblocks, o.dev, s));
+  KLAUNCH("keystream", s, launch_keystream(rk, c->d_T0, domain, block0, nblocks, o.dev, s));
   LWE_CHECK(finish_out(o, s));
   HIP_CHECK(hipStreamSynchronize(s));
   return LWE_OK;
@@ -779,10 +871,10 @@ int lwe_test_sample(lwe_ctx* c, int pid, const uint8_t* key, uint32_t domain, ui
   LWE_CHECK(stage_in(c, B_SEEDA, key, 16, s, &dk));
   uint32_t* rk;
   LWE_CHECK(ensure_t(c, B_RKA, 44 * 4, &rk));
-  HIP_CHECK(launch_expand_keys(dk, 16, 1, c->d_T0, rk, s));
+  KLAUNCH("expand_keys", s, launch_expand_keys(dk, 16, 1, c->d_T0, rk, s));
   OutStage o;
   LWE_CHECK(stage_out(c, B_TEST, out, count * 2, o));
-  HIP_CHECK(launch_sample_stream(*pp, rk, c->d_T0, domain, word0, count, (int16_t*)o.dev, s));
+  KLAUNCH("sample_stream", s, launch_sample_stream(*pp, rk, c->d_T0, domain, word0, count, (int16_t*)o.dev, s));
   LWE_CHECK(finish_out(o, s));
   HIP_CHECK(hipStreamSynchronize(s));
   return LWE_OK;
@@ -805,7 +897,7 @@ int lwe_test_encrypt(lwe_ctx* c, int pid, size_t count, const uint8_t* pk, const
   LWE_CHECK(stage_out(c, B_CT, ct, count * p.ct_bytes, o));
   uint32_t* drk;
   LWE_CHECK(ensure_t(c, B_RK, count * 44 * 4, &drk));
-  HIP_CHECK(launch_expand_keys(dco, 16, (int)count, c->d_T0, drk, s));
+  KLAUNCH("expand_keys", s, launch_expand_keys(dco, 16, (int)count, c->d_T0, drk, s));
   LWE_CHECK(encrypt_core(c, pid, p, count, dpk, drk, dmu, p.mu_bytes, o.dev, nullptr, nullptr, s));
   LWE_CHECK(finish_out(o, s));
   HIP_CHECK(hipStreamSynchronize(s));
@@ -836,7 +928,7 @@ int lwe_test_decrypt(lwe_ctx* c, int pid, size_t count, const uint8_t* sk, const
   da.count = (int)count;
   da.mu_bytes = (int)p.mu_bytes;
   da.mu_out = o.dev;
-  HIP_CHECK(launch_decrypt(da, s));
+  KLAUNCH("decrypt", s, launch_decrypt(da, s));
   LWE_CHECK(finish_out(o, s));
   HIP_CHECK(hipStreamSynchronize(s));
   return LWE_OK;
@@ -851,7 +943,7 @@ int lwe_test_sha3(lwe_ctx* c, size_t count, size_t len, const uint8_t* in, uint8
   LWE_CHECK(stage_in(c, B_CT, in, count * len, s, &din));
   OutStage o;
   LWE_CHECK(stage_out(c, B_TEST, out, count * 32, o));
-  HIP_CHECK(launch_hash_records((int)count, din, len, len, o.dev, s));
+  KLAUNCH("hash_records", s, launch_hash_records((int)count, din, len, len, o.dev, s));
   LWE_CHECK(finish_out(o, s));
   HIP_CHECK(hipStreamSynchronize(s));
   return LWE_OK;

@@ -30,7 +30,11 @@ EXPORTS = [
     "lwe_keygen_batch", "lwe_encaps_batch", "lwe_decaps_batch",
     "lwe_test_expand_A", "lwe_test_keystream", "lwe_test_sample", "lwe_test_encrypt",
     "lwe_test_decrypt", "lwe_test_sha3", "lwe_set_tuning", "lwe_get_tuning",
+    "lwe_prof_enable", "lwe_prof_reset", "lwe_prof_read",
 ]
+
+KERNELS = ["sample", "prod_strip", "prod_stream", "finalize", "decrypt", "fo_coins", "expand_keys",
+           "hash_records", "final_ss", "fill", "keystream", "sample_stream"]
 
 
 class LweLibraryMissing(ImportError):
@@ -106,6 +110,9 @@ def lib() -> C.CDLL:
         "lwe_test_sha3": (i32, [vp, sz, sz, vp, vp, vp]),
         "lwe_set_tuning": (i32, [vp, i32, C.POINTER(Tuning)]),
         "lwe_get_tuning": (i32, [vp, i32, C.POINTER(Tuning)]),
+        "lwe_prof_enable": (i32, [vp, i32]),
+        "lwe_prof_reset": (i32, [vp]),
+        "lwe_prof_read": (i32, [vp, C.c_char_p, C.POINTER(C.c_uint64), C.POINTER(C.c_double)]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -260,6 +267,23 @@ class Context:
         t = Tuning()
         _check(self._lib.lwe_get_tuning(self._h, pid, C.byref(t)), "lwe_get_tuning")
         return {f: getattr(t, f) for f, _ in Tuning._fields_}
+
+    # ---- kernel timing ----
+    def prof_enable(self, on: bool = True) -> None:
+        _check(self._lib.lwe_prof_enable(self._h, 1 if on else 0), "lwe_prof_enable")
+
+    def prof_reset(self) -> None:
+        _check(self._lib.lwe_prof_reset(self._h), "lwe_prof_reset")
+
+    def prof_read(self) -> dict:
+        """{kernel: (launches, total device ms)} for kernels launched since the last reset."""
+        out = {}
+        for k in KERNELS:
+            n, ms = C.c_uint64(), C.c_double()
+            _check(self._lib.lwe_prof_read(self._h, k.encode(), C.byref(n), C.byref(ms)), "lwe_prof_read")
+            if n.value:
+                out[k] = (n.value, ms.value)
+        return out
 
     # ---- KEM (outputs are caller-provided buffers) ----
     def keygen_batch(self, pid, count, seedA, seedSK, z, pk, sk, stream=None):
