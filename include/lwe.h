@@ -156,8 +156,9 @@ int lwe_prof_read(lwe_ctx* ctx, const char* kernel, uint64_t* launches, double* 
 /* Tuning knobs of the batched product kernel (see lwe_tune_* in the Python package).
  * Zero leaves a knob at its built-in default. */
 typedef struct {
-  uint32_t col_groups;   /* 16-column groups per workgroup strip (1, 2 or 4) */
-  uint32_t row_groups;   /* 16-row groups per wave in the streaming loop (1, 2 or 4) */
+  uint32_t col_groups;   /* 16-column groups per workgroup strip (1..4) */
+  uint32_t row_groups;   /* 16-row groups per wave in the streaming loop (1, 2 or 4);
+                            (col_groups, row_groups) pairs: (1..3, 1|2|4), (4, 1|2) */
   uint32_t m_chunks;     /* row chunks sharing one regenerated strip of A */
   uint32_t host_hash_max;/* batches up to this size hash on the host */
 } lwe_tuning;

@@ -32,6 +32,10 @@ struct Buf {
 struct lwe_ctx {
   int device = 0;
   hipStream_t own = nullptr;
+  // second stream for work that overlaps the main one inside a call (decaps hashes the
+  // received ciphertexts while it decrypts and re-encrypts them)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   size_t budget = 0;  // 0 = unlimited
   size_t held = 0;
   uint32_t* d_T0 = nullptr;
@@ -282,13 +286,24 @@ int run_product(lwe_ctx* c, int pid, const Params& p, ProdArgs a, bool trans, hi
     }
     KLAUNCH("prod_stream", s, launch_product_stream(a, CG, RG, W, trans, a.n_mt, KS, s));
   } else {
-    int CG = tu.col_groups ? (int)tu.col_groups : 2;
-    int RG = tu.row_groups ? (int)tu.row_groups : 4;
+    // Default tile: the widest strip of A that fits LDS over the whole contraction (fewer
+    // re-reads of the S' stack), and one row chunk per XCD so that all workgroups of an XCD
+    // stream the same rows of S' through that XCD's L2.
+    int CG = (int)tu.col_groups;
+    if (!CG) {
+      CG = 1;
+      for (int cg = 3; cg >= 1; --cg)
+        if (product_strip_lds_bytes(cg, ksteps * 64) <= 160 * 1024) {
+          CG = cg;
+          break;
+        }
+    }
+    const int RG = tu.row_groups ? (int)tu.row_groups : (CG >= 3 ? 2 : 4);
     const int max_rows = (int)(((160 * 1024 - 4096) / (32 * CG)) / 64 * 64);
     a.kc_len = std::min(ksteps * 64, max_rows);
     a.n_kc = (p.n + a.kc_len - 1) / a.kc_len;
     a.n_jt = (a.ncols + 16 * CG - 1) / (16 * CG);
-    int mch = tu.m_chunks ? (int)tu.m_chunks : std::max(1, (512 + a.n_jt * a.n_kc - 1) / (a.n_jt * a.n_kc) / 2);
+    int mch = tu.m_chunks ? (int)tu.m_chunks : 8;
     const int unit = 16 * RG;
     const int m_units = (a.M + unit - 1) / unit;
     mch = std::min(mch, m_units);
@@ -330,7 +345,7 @@ int encrypt_core(lwe_ctx* c, int pid, const Params& p, size_t count, const uint8
   sa.K = p.K;
   sa.ldx = p.ldx;
   sa.nseg = 3;
-  for (int k = 0; k <= MAX_K; ++k) sa.T[k] = p.T[k];
+  for (int k = 0; k < MAX_K; ++k) sa.T2[k] = (uint32_t)p.T[k] * 0x10001u;
   sa.X = X;
   sa.E = E;
   sa.E2 = E2;
@@ -413,6 +428,9 @@ int lwe_ctx_create(lwe_ctx** out, int device, size_t hbm_budget_bytes) {
   unsigned hc = std::thread::hardware_concurrency();
   c->host_threads = (int)std::max(1u, std::min(hc, 16u));
   if (hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
       hipMalloc(&c->d_T0, 1024) != hipSuccess ||
       hipMemcpy(c->d_T0, aes_T0(), 1024, hipMemcpyHostToDevice) != hipSuccess ||
       init_kernels() != hipSuccess) {
@@ -436,6 +454,9 @@ void lwe_ctx_destroy(lwe_ctx* c) {
     (void)hipEventDestroy(r.b);
   }
   for (auto e : c->prof_pool) (void)hipEventDestroy(e);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  if (c->side) (void)hipStreamDestroy(c->side);
   if (c->own) (void)hipStreamDestroy(c->own);
   delete c;
 }
@@ -515,8 +536,7 @@ int lwe_cdf_table(int pid, uint16_t* T_out, size_t capacity) {
 
 int lwe_set_tuning(lwe_ctx* c, int pid, const lwe_tuning* t) {
   if (!c || !t || !get_params(pid)) return LWE_EINVAL;
-  if (t->col_groups && t->col_groups != 1 && t->col_groups != 2 && t->col_groups != 4) return LWE_EINVAL;
-  if (t->row_groups && t->row_groups != 1 && t->row_groups != 2 && t->row_groups != 4) return LWE_EINVAL;
+  if (t->col_groups > 4 || t->row_groups > 4 || t->row_groups == 3) return LWE_EINVAL;
   if (t->col_groups == 4 && t->row_groups == 4) return LWE_EINVAL;
   c->tuning[pid & 255] = *t;
   return LWE_OK;
@@ -565,7 +585,7 @@ int lwe_keygen_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* seedA, co
   sa.K = p.K;
   sa.ldx = p.ldx;
   sa.nseg = 2;
-  for (int k = 0; k <= MAX_K; ++k) sa.T[k] = p.T[k];
+  for (int k = 0; k < MAX_K; ++k) sa.T2[k] = (uint32_t)p.T[k] * 0x10001u;
   sa.X = X;
   sa.X16 = osk.dev;  // S^T int16 at the start of each sk record
   sa.x16_stride = p.sk_bytes;
@@ -799,13 +819,19 @@ int lwe_decaps_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* sk, const
       HIP_CHECK(hipStreamSynchronize(s));
     }
   } else {
+    // H(ct) of the received ciphertexts does not depend on the decryption: it runs on the
+    // side stream while the main stream decrypts and re-encrypts.
+    uint8_t* dhct;
+    LWE_CHECK(ensure_t(c, B_HCT, count * 32, &dhct));
+    HIP_CHECK(hipEventRecord(c->ev_fork, s));
+    HIP_CHECK(hipStreamWaitEvent(c->side, c->ev_fork, 0));
+    KLAUNCH("hash_records", c->side, launch_hash_records((int)count, dct, p.ct_bytes, p.ct_bytes, dhct, c->side));
+    HIP_CHECK(hipEventRecord(c->ev_join, c->side));
     KLAUNCH("fo_coins", s, launch_fo_coins((int)count, dsk + off_pkh, dmu2, mb, (int)mb, dcoins, dkp, s));
     KLAUNCH("expand_keys", s, launch_expand_keys(dcoins, 16, (int)count, c->d_T0, drk, s));
     KLAUNCH("fill", s, launch_fill_u32(dflags, count, 0, s));
     LWE_CHECK(encrypt_core(c, pid, p, count, dsk + off_pk, drk, dmu2, mb, nullptr, dct, dflags, s));
-    uint8_t* dhct;
-    LWE_CHECK(ensure_t(c, B_HCT, count * 32, &dhct));
-    KLAUNCH("hash_records", s, launch_hash_records((int)count, dct, p.ct_bytes, p.ct_bytes, dhct, s));
+    HIP_CHECK(hipStreamWaitEvent(s, c->ev_join, 0));
     KLAUNCH("final_ss", s, launch_final_ss((int)count, dflags, dkp, dsk + off_z, dhct, oss.dev, s));
   }
   LWE_CHECK(finish_out(oss, s));

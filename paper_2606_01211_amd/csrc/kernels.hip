@@ -31,8 +31,15 @@ __device__ __forceinline__ void load_tables(uint32_t* T, const uint32_t* __restr
   }
 }
 
+// three-input XOR in one v_bitop3 (truth table 0x96)
+__device__ __forceinline__ uint32_t x3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 // Encrypts the CTR counter block of domain `dom` (as its little-endian word) and block
-// index b: the 128-bit big-endian integer dom * 2^96 + b.
+// index b: the 128-bit big-endian integer dom * 2^96 + b.  Per round and column: four
+// table lookups (one shifted-byte address each) folded with the round key by two 3-input
+// XORs.
 template <class RK>
 __device__ __forceinline__ void aes_ctr_block(const uint32_t* __restrict__ T, const RK& rk,
                                               uint32_t dom_le, uint64_t b, uint32_t o[4]) {
@@ -42,14 +49,14 @@ __device__ __forceinline__ void aes_ctr_block(const uint32_t* __restrict__ T, co
   uint32_t s3 = bswap32((uint32_t)b) ^ rk[3];
 #pragma unroll
   for (int r = 1; r < 10; ++r) {
-    const uint32_t t0 = T[s0 & 0xff] ^ T[256 + ((s1 >> 8) & 0xff)] ^ T[512 + ((s2 >> 16) & 0xff)] ^
-                        T[768 + (s3 >> 24)] ^ rk[4 * r];
-    const uint32_t t1 = T[s1 & 0xff] ^ T[256 + ((s2 >> 8) & 0xff)] ^ T[512 + ((s3 >> 16) & 0xff)] ^
-                        T[768 + (s0 >> 24)] ^ rk[4 * r + 1];
-    const uint32_t t2 = T[s2 & 0xff] ^ T[256 + ((s3 >> 8) & 0xff)] ^ T[512 + ((s0 >> 16) & 0xff)] ^
-                        T[768 + (s1 >> 24)] ^ rk[4 * r + 2];
-    const uint32_t t3 = T[s3 & 0xff] ^ T[256 + ((s0 >> 8) & 0xff)] ^ T[512 + ((s1 >> 16) & 0xff)] ^
-                        T[768 + (s2 >> 24)] ^ rk[4 * r + 3];
+    const uint32_t t0 = x3(x3(T[s0 & 0xff], T[256 + ((s1 >> 8) & 0xff)], T[512 + ((s2 >> 16) & 0xff)]),
+                           T[768 + (s3 >> 24)], rk[4 * r]);
+    const uint32_t t1 = x3(x3(T[s1 & 0xff], T[256 + ((s2 >> 8) & 0xff)], T[512 + ((s3 >> 16) & 0xff)]),
+                           T[768 + (s0 >> 24)], rk[4 * r + 1]);
+    const uint32_t t2 = x3(x3(T[s2 & 0xff], T[256 + ((s3 >> 8) & 0xff)], T[512 + ((s0 >> 16) & 0xff)]),
+                           T[768 + (s1 >> 24)], rk[4 * r + 2]);
+    const uint32_t t3 = x3(x3(T[s3 & 0xff], T[256 + ((s0 >> 8) & 0xff)], T[512 + ((s1 >> 16) & 0xff)]),
+                           T[768 + (s2 >> 24)], rk[4 * r + 3]);
     s0 = t0;
     s1 = t1;
     s2 = t2;
@@ -71,6 +78,19 @@ __device__ __forceinline__ void aes_ctr_block(const uint32_t* __restrict__ T, co
          rk[43];
 }
 
+// Round keys are read once into registers before the kernel stores anything, so they stay
+// in scalar registers instead of being re-loaded (as possibly clobbered memory) per block.
+struct RoundKeys {
+  uint32_t w[44];
+  __device__ __forceinline__ uint32_t operator[](int i) const { return w[i]; }
+};
+__device__ __forceinline__ RoundKeys load_rk(const uint32_t* __restrict__ rk) {
+  RoundKeys r;
+#pragma unroll
+  for (int i = 0; i < 44; ++i) r.w[i] = rk[i];
+  return r;
+}
+
 // ======================================================================================
 // Limb split: a 16-bit value x (already reduced mod q) equals lo + 256 hi (mod 2^16) with
 // lo = sext8(x & 0xff) and hi = sext8(((x + 0x80) >> 8) & 0xff).  The int8 byte of lo is the
@@ -88,13 +108,41 @@ __device__ __forceinline__ void limbs4(uint32_t a, uint32_t b, uint32_t& lo, uin
   hi = __builtin_amdgcn_perm(b2, a2, 0x07050301u);
 }
 
-__device__ __forceinline__ uint32_t sample_one(uint32_t u, const uint16_t* T, int K) {
+// |e| = #{k < K : (u >> 1) > T[k]}, sign from bit 0.  KT > 0: support fixed at compile time;
+// KT == 0: K is a (uniform) run-time value.  Every entry is compared: no early exit.
+template <int KT>
+__device__ __forceinline__ uint32_t sample_one_t(uint32_t u, const uint16_t* T, int K) {
   const uint32_t r = u >> 1;
   int e = 0;
+  if constexpr (KT > 0) {
 #pragma unroll
-  for (int k = 0; k < MAX_K; ++k)
-    if (k < K) e += (r > T[k]) ? 1 : 0;
+    for (int k = 0; k < KT; ++k) e += (r > (uint32_t)T[k]) ? 1 : 0;
+  } else {
+    for (int k = 0; k < K; ++k) e += (r > (uint32_t)T[k]) ? 1 : 0;
+  }
   return (uint32_t)(uint8_t)(int8_t)((u & 1) ? -e : e);
+}
+
+__device__ __forceinline__ uint32_t sample_one(uint32_t u, const uint16_t* T, int K) {
+  return sample_one_t<0>(u, T, K);
+}
+
+// Two samples at once from one keystream word pair w = u0 | u1 << 16, in packed 16-bit
+// arithmetic: r > T[k] exactly when T[k] - r (both < 2^15) has bit 15 set.  T2[k] holds T[k]
+// in both halves.  Returns the two signed samples as int16 halves (two's complement).
+template <int KT>
+__device__ __forceinline__ uint32_t sample_pair(uint32_t w, const uint32_t* T2, int K) {
+  const v2u16 u = __builtin_bit_cast(v2u16, w);
+  const v2u16 r = u >> (v2u16){1, 1};
+  v2u16 e = {0, 0};
+  if constexpr (KT > 0) {
+#pragma unroll
+    for (int k = 0; k < KT; ++k) e += (__builtin_bit_cast(v2u16, T2[k]) - r) >> (v2u16){15, 15};
+  } else {
+    for (int k = 0; k < K; ++k) e += (__builtin_bit_cast(v2u16, T2[k]) - r) >> (v2u16){15, 15};
+  }
+  const v2u16 m = (v2u16){0, 0} - (u & (v2u16){1, 1});  // 0xffff where the sign bit is set
+  return __builtin_bit_cast(uint32_t, (v2u16)((e ^ m) - m));
 }
 
 // ======================================================================================
@@ -128,8 +176,9 @@ __global__ void k_keystream(const uint32_t* __restrict__ rk, const uint32_t* __r
   __syncthreads();
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nblocks) return;
+  const RoundKeys rkv = load_rk(rk);
   uint32_t o[4];
-  aes_ctr_block(T, rk, dom_le, block0 + t, o);
+  aes_ctr_block(T, rkv, dom_le, block0 + t, o);
   uint4 v = make_uint4(o[0], o[1], o[2], o[3]);
   *(uint4*)(out + 16 * t) = v;
 }
@@ -146,8 +195,9 @@ __global__ void k_expand_A(int n, uint32_t qmask2, const uint32_t* __restrict__ 
   if (t >= (size_t)ncols * bpc) return;
   const size_t c = t / bpc, kb = t % bpc;
   const uint64_t b = ((uint64_t)col0 + c) * bpc + kb;
+  const RoundKeys rkv = load_rk(rk);
   uint32_t o[4];
-  aes_ctr_block(T, rk, 0u, b, o);
+  aes_ctr_block(T, rkv, 0u, b, o);
   uint4 v = make_uint4(o[0] & qmask2, o[1] & qmask2, o[2] & qmask2, o[3] & qmask2);
   *(uint4*)(out + c * n + 8 * kb) = v;
 }
@@ -165,8 +215,9 @@ __global__ void k_sample_stream(SampTable st, int K, const uint32_t* __restrict_
   const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= count) return;
   const uint64_t w = word0 + t;
+  const RoundKeys rkv = load_rk(rk);
   uint32_t o[4];
-  aes_ctr_block(T, rk, dom_le, w / 8, o);
+  aes_ctr_block(T, rkv, dom_le, w / 8, o);
   const uint32_t u = (o[(w % 8) >> 1] >> (16 * (w & 1))) & 0xffffu;
   out[t] = (int16_t)(int8_t)(uint8_t)sample_one(u, st.T, K);
 }
@@ -176,10 +227,11 @@ __global__ void k_sample_stream(SampTable st, int K, const uint32_t* __restrict_
 // instance.  Keystream domains: 1 -> segment 0, 2 -> segment 1, 3 -> segment 2.  Every AES
 // block gives 8 consecutive samples of one matrix row.
 // ======================================================================================
+template <int KT>
 __global__ void __launch_bounds__(256) k_sample(SampleArgs a) {
   __shared__ uint32_t T[1024];
   const int inst = blockIdx.y;
-  const uint32_t* __restrict__ rk = a.rk + (size_t)inst * 44;
+  const RoundKeys rk = load_rk(a.rk + (size_t)inst * 44);
   load_tables(T, a.T0);
   const int n = a.n;
   if (blockIdx.x == 0 && a.ldx > n) {  // zero the padding columns of segment 0
@@ -204,26 +256,18 @@ __global__ void __launch_bounds__(256) k_sample(SampleArgs a) {
     }
     uint32_t o[4];
     aes_ctr_block(T, rk, bswap32((uint32_t)(seg + 1)), (uint64_t)lb, o);
-    uint32_t e[8];
+    uint32_t h[4];  // samples 2k, 2k+1 as int16 halves
 #pragma unroll
-    for (int w = 0; w < 8; ++w) e[w] = sample_one((o[w >> 1] >> (16 * (w & 1))) & 0xffffu, a.T, a.K);
-    const uint32_t p0 = e[0] | (e[1] << 8) | (e[2] << 16) | (e[3] << 24);
-    const uint32_t p1 = e[4] | (e[5] << 8) | (e[6] << 16) | (e[7] << 24);
+    for (int q = 0; q < 4; ++q) h[q] = sample_pair<KT>(o[q], a.T2, a.K);
+    const uint32_t p0 = __builtin_amdgcn_perm(h[1], h[0], 0x06040200u);  // low bytes = int8 samples
+    const uint32_t p1 = __builtin_amdgcn_perm(h[3], h[2], 0x06040200u);
     const int w0 = 8 * lb;
     if (seg == 0) {
       const int row = w0 / n, col = w0 % n;
       *(uint2*)(a.X + ((size_t)inst * 8 + row) * a.ldx + col) = make_uint2(p0, p1);
-      if (a.X16) {
-        uint32_t h[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const uint32_t lo = (uint32_t)(uint16_t)(int16_t)(int8_t)(uint8_t)e[2 * k];
-          const uint32_t hi = (uint32_t)(uint16_t)(int16_t)(int8_t)(uint8_t)e[2 * k + 1];
-          h[k] = lo | (hi << 16);
-        }
+      if (a.X16)
         *(uint4*)(a.X16 + (size_t)inst * a.x16_stride + 2 * ((size_t)row * n + col)) =
             make_uint4(h[0], h[1], h[2], h[3]);
-      }
     } else if (seg == 1) {
       const int row = w0 / n, col = w0 % n;
       *(uint2*)(a.E + ((size_t)inst * 8 + row) * n + col) = make_uint2(p0, p1);
@@ -304,7 +348,7 @@ __global__ void __launch_bounds__(1024) k_prod_stream(ProdArgs a, int ks_per_wav
   uint8_t* tr = (uint8_t*)(red + (size_t)W * RG * CG * 256);    // TRANS: [W][2][CG][16][64]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int jt = blockIdx.x % a.n_jt, kc = blockIdx.x / a.n_jt, mt = blockIdx.y;
-  const uint32_t* __restrict__ rk = a.rkA + (a.per_inst_A ? (size_t)mt * 44 : 0);
+  const RoundKeys rk = load_rk(a.rkA + (a.per_inst_A ? (size_t)mt * 44 : 0));
   const int n = a.n;
   const int m_begin = mt * a.m_tile, m_end = min(a.M, m_begin + a.m_tile);
   const int nn0 = jt * 16 * CG;
@@ -453,14 +497,23 @@ __global__ void __launch_bounds__(1024) k_prod_stream(ProdArgs a, int ks_per_wav
 // ======================================================================================
 // Product, strip form (large row counts: batched encryption against one public key).
 // The workgroup regenerates a strip of A (all contraction rows of the K chunk x 16*CG
-// columns) into LDS once, already split into limbs and laid out as MFMA B fragments, and
-// then streams every row tile of its row chunk through it.
+// columns) into LDS once, already split into limbs and laid out as MFMA fragments, and
+// then streams every row tile of its row chunk through it.  The MFMA computes the
+// transposed tile (A strip as the first operand), so each lane ends up holding four
+// consecutive columns of one output row: the epilogue reads E' four bytes and writes the
+// result eight bytes at a time.
 //   LDS: [ksteps][CG][limb][64 lanes][16 bytes] after the 4 KB of AES tables.
 // Workgroup ids are remapped so that each XCD (ids congruent mod 8) processes a
 // contiguous range of tiles, i.e. the same row chunks share that XCD's L2.
 // ======================================================================================
+constexpr int STRIP_WAVES = 8;
+
+__device__ __forceinline__ v4i load_x(const int8_t* p, bool v) {
+  return v ? *(const v4i*)p : v4i{0, 0, 0, 0};
+}
+
 template <int CG, int RG>
-__global__ void __launch_bounds__(256) k_prod_strip(ProdArgs a) {
+__global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
   extern __shared__ uint32_t smem[];
   uint32_t* T = smem;
   uint8_t* strip = (uint8_t*)(smem + 1024);
@@ -477,8 +530,9 @@ __global__ void __launch_bounds__(256) k_prod_strip(ProdArgs a) {
   const int k0 = kc * a.kc_len;
   const int k_len = min(a.kc_len, n - k0);
   const int ksteps = (k_len + 63) >> 6;
-  const uint32_t qmask2 = ((1u << a.logq) - 1u) * 0x10001u;
-  const uint32_t* __restrict__ rk = a.rkA;
+  const uint32_t qmask = (1u << a.logq) - 1u;
+  const uint32_t qmask2 = qmask * 0x10001u;
+  const RoundKeys rk = load_rk(a.rkA);
 
   load_tables(T, a.T0);
   __syncthreads();
@@ -512,7 +566,7 @@ __global__ void __launch_bounds__(256) k_prod_strip(ProdArgs a) {
   const int m_begin = mt * a.m_tile, m_end = min(a.M, m_begin + a.m_tile);
   const int rows = m_end - m_begin;
   const int nrb = (rows + 16 * RG - 1) / (16 * RG);
-  for (int rb = wave; rb < nrb; rb += 4) {
+  for (int rb = wave; rb < nrb; rb += STRIP_WAVES) {
     v4i acc[RG][CG][2];
 #pragma unroll
     for (int rg = 0; rg < RG; ++rg)
@@ -527,48 +581,79 @@ __global__ void __launch_bounds__(256) k_prod_strip(ProdArgs a) {
       xv[rg] = row < m_end;
       xp[rg] = a.X + (size_t)(xv[rg] ? row : m_begin) * a.ldx + k0 + 16 * (lane >> 4);
     }
-    v4i xf[RG], xn[RG];
+    // X fragments for steps s, s+1, s+2 in flight
+    v4i x0[RG], x1[RG], x2[RG];
 #pragma unroll
-    for (int rg = 0; rg < RG; ++rg) xf[rg] = xv[rg] ? *(const v4i*)xp[rg] : v4i{0, 0, 0, 0};
+    for (int rg = 0; rg < RG; ++rg) {
+      x0[rg] = load_x(xp[rg], xv[rg]);
+      x1[rg] = load_x(xp[rg] + 64, xv[rg] && ksteps > 1);
+    }
     for (int s = 0; s < ksteps; ++s) {
-      if (s + 1 < ksteps) {
 #pragma unroll
-        for (int rg = 0; rg < RG; ++rg)
-          xn[rg] = xv[rg] ? *(const v4i*)(xp[rg] + 64 * (s + 1)) : v4i{0, 0, 0, 0};
-      }
+      for (int rg = 0; rg < RG; ++rg) x2[rg] = load_x(xp[rg] + 64 * (s + 2), xv[rg] && s + 2 < ksteps);
 #pragma unroll
       for (int cg = 0; cg < CG; ++cg) {
         const v4i ylo = *(const v4i*)(strip + ((size_t)((s * CG + cg) * 2) * 64 + lane) * 16);
         const v4i yhi = *(const v4i*)(strip + ((size_t)((s * CG + cg) * 2 + 1) * 64 + lane) * 16);
 #pragma unroll
         for (int rg = 0; rg < RG; ++rg) {
-          acc[rg][cg][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(xf[rg], ylo, acc[rg][cg][0], 0, 0, 0);
-          acc[rg][cg][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(xf[rg], yhi, acc[rg][cg][1], 0, 0, 0);
+          acc[rg][cg][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ylo, x0[rg], acc[rg][cg][0], 0, 0, 0);
+          acc[rg][cg][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(yhi, x0[rg], acc[rg][cg][1], 0, 0, 0);
         }
       }
-      if (s + 1 < ksteps) {
 #pragma unroll
-        for (int rg = 0; rg < RG; ++rg) xf[rg] = xn[rg];
+      for (int rg = 0; rg < RG; ++rg) {
+        x0[rg] = x1[rg];
+        x1[rg] = x2[rg];
       }
     }
+    // epilogue: lane holds columns 4*(lane>>4) .. +3 of row (lane & 15) of each 16x16 tile
 #pragma unroll
     for (int rg = 0; rg < RG; ++rg) {
+      const int row = rbase + rg * 16 + (lane & 15);
+      const bool rvalid = row < m_end;
+      const int inst = row >> 3, r = row & 7;
       uint32_t mism = 0;
-      const int row_base = rbase + rg * 16;
 #pragma unroll
-      for (int cg = 0; cg < CG; ++cg)
+      for (int cg = 0; cg < CG; ++cg) {
+        const int col0 = nn0 + cg * 16 + 4 * (lane >> 4);
+        uint32_t D[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int row = row_base + 4 * (lane >> 4) + i;
-          const int col = nn0 + cg * 16 + (lane & 15);
-          if (row >= m_end || col >= a.ncols) continue;
-          const uint32_t D = (uint32_t)acc[rg][cg][0][i] + ((uint32_t)acc[rg][cg][1][i] << 8);
-          if (a.n_kc > 1)
-            atomicAdd((uint32_t*)&a.acc32[(size_t)row * a.acc_ld + col], D);
-          else
-            mism |= epi_store(a, row, col, D);
+        for (int i = 0; i < 4; ++i)
+          D[i] = (uint32_t)acc[rg][cg][0][i] + ((uint32_t)acc[rg][cg][1][i] << 8);
+        if (!rvalid) continue;
+        if (a.n_kc > 1) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (col0 + i < a.ncols) atomicAdd((uint32_t*)&a.acc32[(size_t)row * a.acc_ld + col0 + i], D[i]);
+        } else if (col0 + 4 <= n) {
+          const uint32_t e4 = *(const uint32_t*)(a.E + (size_t)row * n + col0);
+          uint32_t v4[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) v4[i] = (D[i] + (uint32_t)(int32_t)(int8_t)(e4 >> (8 * i))) & qmask;
+          const uint2 packed = make_uint2(v4[0] | (v4[1] << 16), v4[2] | (v4[3] << 16));
+          const size_t off = a.out_off + 2 * ((size_t)r * n + col0);
+          if (a.mode == PM_COMPARE) {
+            const uint2 got = *(const uint2*)(a.cmp + (size_t)inst * a.cmp_stride + off);
+            mism |= (got.x ^ packed.x) | (got.y ^ packed.y);
+          } else {
+            *(uint2*)(a.out + (size_t)inst * a.out_stride + off) = packed;
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (col0 + i < a.ncols) mism |= epi_store(a, row, col0 + i, D[i]);
         }
-      if (a.mode == PM_COMPARE && a.n_kc == 1) flag_tile(a, row_base, mism);
+      }
+      if (a.mode == PM_COMPARE && a.n_kc == 1) {
+        // rows 0-7 of the tile (lanes with (lane & 15) < 8) are one instance, rows 8-15 the next
+        const uint64_t bal = __ballot(mism != 0);
+        const int row_base = rbase + rg * 16;
+        if (lane == 0 && row_base < a.M)
+          atomicOr(&a.flags[row_base >> 3], (uint32_t)((bal & 0x00FF00FF00FF00FFull) != 0));
+        if (lane == 8 && row_base + 8 < a.M)
+          atomicOr(&a.flags[(row_base >> 3) + 1], (uint32_t)((bal & 0xFF00FF00FF00FF00ull) != 0));
+      }
     }
   }
 }
@@ -702,31 +787,243 @@ __global__ void k_fo_coins(int count, const uint8_t* __restrict__ pkh, const uin
   for (int k = 0; k < 32; ++k) kprime[(size_t)i * 32 + k] = h[k];
 }
 
-// SHA3-256 of count records of len bytes; 8-byte loads when the layout allows it.
-__global__ void k_hash_records(int count, const uint8_t* __restrict__ in, size_t stride, size_t len,
-                               uint8_t* out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
-  const uint8_t* p = in + (size_t)i * stride;
-  uint64_t a[25];
+// Keccak-f[1600] on 32-bit halves: lane (x, y) is (hi[x + 5y], lo[x + 5y]).  Written with the
+// gfx950 three-input bit operations: a 3-way XOR (LUT 0x96) and chi's a ^ (~b & c) (LUT 0xD2),
+// and 64-bit rotations as two funnel shifts (v_alignbit).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+__device__ __forceinline__ uint32_t chi3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0xD2);
+}
+// rotate the 64-bit value (hi, lo) left by r, 0 < r < 64, r != 32
+__device__ __forceinline__ void rotl64_32(uint32_t hi, uint32_t lo, int r, uint32_t& oh, uint32_t& ol) {
+  if (r < 32) {
+    oh = __builtin_amdgcn_alignbit(hi, lo, 32 - r);
+    ol = __builtin_amdgcn_alignbit(lo, hi, 32 - r);
+  } else {
+    oh = __builtin_amdgcn_alignbit(lo, hi, 64 - r);
+    ol = __builtin_amdgcn_alignbit(hi, lo, 64 - r);
+  }
+}
+
+__device__ __forceinline__ void keccak_f1600_dev(uint32_t lo[25], uint32_t hi[25]) {
+#pragma unroll 1
+  for (int round = 0; round < 24; ++round) {
+    uint32_t cl[5], ch[5];
 #pragma unroll
-  for (int k = 0; k < 25; ++k) a[k] = 0;
-  const bool aligned = (((uintptr_t)p) & 7) == 0;
+    for (int x = 0; x < 5; ++x) {
+      cl[x] = xor3(xor3(lo[x], lo[x + 5], lo[x + 10]), lo[x + 15], lo[x + 20]);
+      ch[x] = xor3(xor3(hi[x], hi[x + 5], hi[x + 10]), hi[x + 15], hi[x + 20]);
+    }
+#pragma unroll
+    for (int x = 0; x < 5; ++x) {
+      uint32_t rh, rl;
+      rotl64_32(ch[(x + 1) % 5], cl[(x + 1) % 5], 1, rh, rl);
+#pragma unroll
+      for (int y = 0; y < 5; ++y) {
+        lo[x + 5 * y] = xor3(lo[x + 5 * y], cl[(x + 4) % 5], rl);
+        hi[x + 5 * y] = xor3(hi[x + 5 * y], ch[(x + 4) % 5], rh);
+      }
+    }
+    uint32_t bl[25], bh[25];
+#pragma unroll
+    for (int x = 0; x < 5; ++x)
+#pragma unroll
+      for (int y = 0; y < 5; ++y) {
+        const int r = keccak_rho(x + 5 * y), d = y + 5 * ((2 * x + 3 * y) % 5);
+        if (r == 0) {
+          bl[d] = lo[x + 5 * y];
+          bh[d] = hi[x + 5 * y];
+        } else {
+          rotl64_32(hi[x + 5 * y], lo[x + 5 * y], r, bh[d], bl[d]);
+        }
+      }
+#pragma unroll
+    for (int y = 0; y < 5; ++y)
+#pragma unroll
+      for (int x = 0; x < 5; ++x) {
+        lo[x + 5 * y] = chi3(bl[x + 5 * y], bl[(x + 1) % 5 + 5 * y], bl[(x + 2) % 5 + 5 * y]);
+        hi[x + 5 * y] = chi3(bh[x + 5 * y], bh[(x + 1) % 5 + 5 * y], bh[(x + 2) % 5 + 5 * y]);
+      }
+    const uint64_t rc = keccak_rc(round);
+    lo[0] ^= (uint32_t)rc;
+    hi[0] ^= (uint32_t)(rc >> 32);
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Two-lane bit-interleaved Keccak-f[1600].  A pair of adjacent lanes holds one state: lane
+// parity 0 keeps the even bits of every 64-bit lane word, parity 1 the odd bits, each as a
+// 32-bit word.  XOR, AND and chi act on the halves independently; a 64-bit rotation by
+// 2k rotates both halves by k, and a rotation by 2k+1 swaps the halves between the two
+// lanes (one DPP move) with rotations by k+1 (even half) and k (odd half).
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t swap_pair(uint32_t v) {
+  // quad_perm [1, 0, 3, 2]: exchange with the adjacent lane
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t rot32(uint32_t v, uint32_t s) { return __builtin_amdgcn_alignbit(v, v, s); }
+
+// even / odd halves of the round constants
+__device__ __forceinline__ uint32_t keccak_rc_half(int round, int parity) {
+  constexpr uint32_t rce[24] = {0x00000001u, 0x00000000u, 0x00000000u, 0x00000000u, 0x00000001u, 0x00000001u,
+                                0x00000001u, 0x00000001u, 0x00000000u, 0x00000000u, 0x00000001u, 0x00000000u,
+                                0x00000001u, 0x00000001u, 0x00000001u, 0x00000001u, 0x00000000u, 0x00000000u,
+                                0x00000000u, 0x00000000u, 0x00000001u, 0x00000000u, 0x00000001u, 0x00000000u};
+  constexpr uint32_t rco[24] = {0x00000000u, 0x00000089u, 0x8000008bu, 0x80008080u, 0x0000008bu, 0x00008000u,
+                                0x80008088u, 0x80000082u, 0x0000000bu, 0x0000000au, 0x00008082u, 0x00008003u,
+                                0x0000808bu, 0x8000000bu, 0x8000008au, 0x80000081u, 0x80000081u, 0x80000008u,
+                                0x00000083u, 0x80008003u, 0x80008088u, 0x80000088u, 0x00008000u, 0x80008082u};
+  return parity ? rco[round] : rce[round];
+}
+
+__device__ __forceinline__ void keccak_f1600_pair(uint32_t s[25], uint32_t p) {
+  const uint32_t sh1 = p ? 0u : 31u;  // rotation of the partner's C[x+1] by 1 (even half) or 0
+#pragma unroll 1
+  for (int round = 0; round < 24; ++round) {
+    uint32_t c[5];
+#pragma unroll
+    for (int x = 0; x < 5; ++x) c[x] = xor3(xor3(s[x], s[x + 5], s[x + 10]), s[x + 15], s[x + 20]);
+#pragma unroll
+    for (int x = 0; x < 5; ++x) {
+      const uint32_t rc = rot32(swap_pair(c[(x + 1) % 5]), sh1);
+#pragma unroll
+      for (int y = 0; y < 5; ++y) s[x + 5 * y] = xor3(s[x + 5 * y], c[(x + 4) % 5], rc);
+    }
+    uint32_t b[25];
+#pragma unroll
+    for (int x = 0; x < 5; ++x)
+#pragma unroll
+      for (int y = 0; y < 5; ++y) {
+        const int r = keccak_rho(x + 5 * y), d = y + 5 * ((2 * x + 3 * y) % 5);
+        const uint32_t v = s[x + 5 * y];
+        if ((r & 1) == 0) {
+          const int kk = r >> 1;
+          b[d] = kk ? rot32(v, (uint32_t)(32 - kk)) : v;
+        } else {
+          const int kk = r >> 1;  // even half rotates by kk + 1, odd half by kk
+          b[d] = rot32(swap_pair(v), (uint32_t)(31 - kk) + p);
+        }
+      }
+#pragma unroll
+    for (int y = 0; y < 5; ++y)
+#pragma unroll
+      for (int x = 0; x < 5; ++x)
+        s[x + 5 * y] = chi3(b[x + 5 * y], b[(x + 1) % 5 + 5 * y], b[(x + 2) % 5 + 5 * y]);
+    s[0] ^= keccak_rc_half(round, (int)p);
+  }
+}
+
+// bit_permute_step of the even/odd separation network
+__device__ __forceinline__ uint32_t perm_step(uint32_t x, uint32_t m, int sh) {
+  const uint32_t t = __builtin_amdgcn_bitop3_b32(x >> sh, x, m, 0x28);  // ((x >> sh) ^ x) & m
+  return xor3(x, t, t << sh);
+}
+// 32-bit word -> even bits in the low half, odd bits in the high half
+__device__ __forceinline__ uint32_t unshuffle32(uint32_t x) {
+  x = perm_step(x, 0x22222222u, 1);
+  x = perm_step(x, 0x0c0c0c0cu, 2);
+  x = perm_step(x, 0x00f000f0u, 4);
+  return perm_step(x, 0x0000ff00u, 8);
+}
+__device__ __forceinline__ uint32_t shuffle32(uint32_t x) {
+  x = perm_step(x, 0x0000ff00u, 8);
+  x = perm_step(x, 0x00f000f0u, 4);
+  x = perm_step(x, 0x0c0c0c0cu, 2);
+  return perm_step(x, 0x22222222u, 1);
+}
+// Lane p holds 32-bit half p of a 64-bit message word; returns its interleaved half.
+__device__ __forceinline__ uint32_t interleave_in(uint32_t w, uint32_t sel) {
+  const uint32_t u = unshuffle32(w);
+  const uint32_t v = swap_pair(u);
+  // parity 0: (u & 0xffff) | (v << 16); parity 1: (v >> 16) | (u & 0xffff0000)
+  return __builtin_amdgcn_perm(sel ? u : v, sel ? v : u, sel ? 0x07060302u : 0x05040100u);
+}
+
+// SHA3-256 of count records of len bytes, one record per pair of lanes.  Full 136-byte
+// blocks are read as 4-byte words (when aligned) and the next block is fetched while the
+// current one is permuted; the final block and the padding are assembled byte by byte.
+__global__ void __launch_bounds__(64) k_hash_records(int count, const uint8_t* __restrict__ in, size_t stride,
+                                                     size_t len, uint8_t* out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t p = (uint32_t)(t & 1);
+  const int rec_raw = t >> 1;
+  const bool valid = rec_raw < count;
+  const int rec = valid ? rec_raw : count - 1;  // idle pairs shadow the last record (no store)
+  const uint8_t* base = in + (size_t)rec * stride;
+  uint32_t s[25];
+#pragma unroll
+  for (int k = 0; k < 25; ++k) s[k] = 0;
+  const size_t nfull = len / SHA3_RATE;
+  const bool aligned = (((uintptr_t)base) & 3) == 0;
   size_t off = 0;
-  for (; off + SHA3_RATE <= len; off += SHA3_RATE) {
-    if (aligned) {
-      const uint64_t* q = (const uint64_t*)(p + off);
+  if (aligned && nfull > 0) {
+    const uint32_t* q = (const uint32_t*)base + p;
+    uint32_t cur[17], nxt[17];
 #pragma unroll
-      for (int w = 0; w < SHA3_RATE / 8; ++w) a[w] ^= q[w];
-      keccak_f1600(a);
-    } else {
-      sha3_absorb_full(a, p + off);
+    for (int w = 0; w < 17; ++w) cur[w] = q[2 * w];
+    for (size_t b = 0; b < nfull; ++b) {
+      const bool more = b + 1 < nfull;
+      const uint32_t* qn = q + (b + 1) * (SHA3_RATE / 4);
+#pragma unroll
+      for (int w = 0; w < 17; ++w) nxt[w] = more ? qn[2 * w] : 0u;
+#pragma unroll
+      for (int w = 0; w < 17; ++w) s[w] ^= interleave_in(cur[w], p);
+      keccak_f1600_pair(s, p);
+#pragma unroll
+      for (int w = 0; w < 17; ++w) cur[w] = nxt[w];
+    }
+    off = nfull * SHA3_RATE;
+  } else {
+    for (size_t b = 0; b < nfull; ++b, off += SHA3_RATE) {
+#pragma unroll
+      for (int w = 0; w < 17; ++w) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) v |= (uint32_t)base[off + 8 * w + 4 * p + kb] << (8 * kb);
+        s[w] ^= interleave_in(v, p);
+      }
+      keccak_f1600_pair(s, p);
     }
   }
-  sha3_absorb_last(a, p + off, len - off);
-  uint8_t h[32];
-  sha3_squeeze32(a, h);
-  for (int k = 0; k < 32; ++k) out[(size_t)i * 32 + k] = h[k];
+  // final block: remaining bytes, the domain bits 01 and pad10*1
+  const int rem = (int)(len - off);
+#pragma unroll
+  for (int w = 0; w < 17; ++w) {
+    uint32_t v = 0;
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+      const int pos = 8 * w + 4 * (int)p + kb;
+      uint32_t byte = pos < rem ? (uint32_t)base[off + pos] : 0u;
+      if (pos == rem) byte ^= 0x06u;
+      if (pos == SHA3_RATE - 1) byte ^= 0x80u;
+      v |= byte << (8 * kb);
+    }
+    s[w] ^= interleave_in(v, p);
+  }
+  keccak_f1600_pair(s, p);
+  // digest: words 0..3 re-interleaved by the even lane
+  uint32_t d[8];
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    // the exchange runs on every lane (a DPP read from a lane masked off by a branch would
+    // not see the partner); only the selection depends on the parity
+    const uint32_t sw = swap_pair(s[w]);
+    const uint32_t e = p ? sw : s[w];
+    const uint32_t o = p ? s[w] : sw;
+    d[2 * w] = shuffle32((e & 0xffffu) | (o << 16));
+    d[2 * w + 1] = shuffle32((e >> 16) | (o & 0xffff0000u));
+  }
+  if (!valid || p) return;
+  uint8_t* dst = out + (size_t)rec * 32;
+  if ((((uintptr_t)dst) & 15) == 0) {
+    *(uint4*)dst = make_uint4(d[0], d[1], d[2], d[3]);
+    *(uint4*)(dst + 16) = make_uint4(d[4], d[5], d[6], d[7]);
+  } else {
+#pragma unroll
+    for (int kb = 0; kb < 32; ++kb) dst[kb] = (uint8_t)(d[kb / 4] >> (8 * (kb % 4)));
+  }
 }
 
 // ss = H(pre || H(ct)) with pre = K' (accepted) or z (rejected), selected without branches.
@@ -800,7 +1097,13 @@ hipError_t launch_sample(const SampleArgs& a, int count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   const int total = 2 * a.n + (a.nseg == 3 ? 8 : 0);
   const unsigned gx = (unsigned)((total + a.chunk - 1) / a.chunk);
-  hipLaunchKernelGGL(k_sample, dim3(gx, (unsigned)count), dim3(256), 0, s, a);
+  const dim3 grid(gx, (unsigned)count);
+  switch (a.K) {
+    case 6: hipLaunchKernelGGL(k_sample<6>, grid, dim3(256), 0, s, a); break;
+    case 10: hipLaunchKernelGGL(k_sample<10>, grid, dim3(256), 0, s, a); break;
+    case 12: hipLaunchKernelGGL(k_sample<12>, grid, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL(k_sample<0>, grid, dim3(256), 0, s, a); break;
+  }
   return hipGetLastError();
 }
 
@@ -838,7 +1141,7 @@ static hipError_t launch_strip_t(const ProdArgs& a, hipStream_t s) {
   const size_t lds = product_strip_lds_bytes(CG, a.kc_len);
   const int total = a.n_jt * a.n_kc * a.n_mt;
   const unsigned grid = (unsigned)(8 * ((total + 7) / 8));
-  hipLaunchKernelGGL((k_prod_strip<CG, RG>), dim3(grid), dim3(256), lds, s, a);
+  hipLaunchKernelGGL((k_prod_strip<CG, RG>), dim3(grid), dim3(64 * STRIP_WAVES), lds, s, a);
   return hipGetLastError();
 }
 
@@ -851,6 +1154,9 @@ hipError_t launch_product_strip(const ProdArgs& a, int cg, int rg, hipStream_t s
   LWE_STRIP_CASE(2, 1)
   LWE_STRIP_CASE(2, 2)
   LWE_STRIP_CASE(2, 4)
+  LWE_STRIP_CASE(3, 1)
+  LWE_STRIP_CASE(3, 2)
+  LWE_STRIP_CASE(3, 4)
   LWE_STRIP_CASE(4, 1)
   LWE_STRIP_CASE(4, 2)
 #undef LWE_STRIP_CASE
@@ -881,7 +1187,7 @@ hipError_t launch_fo_coins(int count, const uint8_t* pkh, const uint8_t* mu, siz
 hipError_t launch_hash_records(int count, const uint8_t* in, size_t stride, size_t len, uint8_t* out,
                                hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_hash_records, dim3(nblk(count, 64)), dim3(64), 0, s, count, in, stride, len, out);
+  hipLaunchKernelGGL(k_hash_records, dim3(nblk(2 * (size_t)count, 64)), dim3(64), 0, s, count, in, stride, len, out);
   return hipGetLastError();
 }
 
@@ -913,6 +1219,9 @@ hipError_t init_kernels() {
   LWE_TRY((allow_lds_strip<2, 1>()))
   LWE_TRY((allow_lds_strip<2, 2>()))
   LWE_TRY((allow_lds_strip<2, 4>()))
+  LWE_TRY((allow_lds_strip<3, 1>()))
+  LWE_TRY((allow_lds_strip<3, 2>()))
+  LWE_TRY((allow_lds_strip<3, 4>()))
   LWE_TRY((allow_lds_strip<4, 1>()))
   LWE_TRY((allow_lds_strip<4, 2>()))
   LWE_TRY((allow_lds_stream<1, 1, false>()))

@@ -57,7 +57,7 @@ struct SampleArgs {
   const uint32_t* T0;
   int n, K, ldx;
   int nseg;              // 2 (keygen: S^T, E^T) or 3 (encryption: S', E', E'')
-  uint16_t T[MAX_K + 1];
+  uint32_t T2[MAX_K];    // CDF entries T[0..K-1], each replicated in both 16-bit halves
   int8_t* X;             // segment 0 (domain 1): [count*8][ldx]
   uint8_t* X16;          // optional int16 copy of segment 0 (secret key bytes), may be null
   size_t x16_stride;

@@ -1,0 +1,394 @@
+"""Continuous-batching KEM server over the C ABI.
+
+Requests (KeyGen, Encaps, Decaps) of different lattice dimensions arrive at any time.  A
+scheduler thread groups the queued requests that can share one library call -- the same
+operation, dimension and (for Encaps / Decaps) the same resident key pair -- and hands each
+group to one of several worker lanes.  Every lane owns its own library context and HIP
+stream, so batches of different lanes run concurrently on the device, and a request that
+arrives while others are in flight joins the next group as soon as a lane and enough device
+memory are free.  Admission is by HBM footprint: the bytes a batch needs are reserved
+against the server's budget before it is dispatched and released when it completes; a group
+that does not fit is split, and a single request that can never fit fails alone with
+LWE_ENOMEM.
+
+Key pairs are generated once at start-up and stay resident on the device (torch uint8
+tensors); only messages, ciphertexts and shared secrets cross PCIe.
+
+Latency of a request = completion time - arrival time (the time submit() was called, or the
+arrival stamp supplied by a load generator).  The scheduler never changes the arithmetic:
+each request's result is byte-identical to the same request executed alone.
+"""
+from __future__ import annotations
+
+import collections
+import concurrent.futures as cf
+import threading
+import time
+from dataclasses import dataclass, field
+from typing import Callable, Dict, List, Optional, Tuple
+
+import numpy as np
+
+KEYGEN, ENCAPS, DECAPS = 0, 1, 2
+OP_NAMES = {KEYGEN: "keygen", ENCAPS: "encaps", DECAPS: "decaps"}
+
+
+@dataclass
+class Request:
+    op: int
+    n: int
+    key: int                       # resident key pair index (Encaps / Decaps); ignored for KeyGen
+    payload: Tuple                 # KeyGen: (seedA, seedSK, z); Encaps: (mu,); Decaps: (ct,)
+    arrival: float = 0.0           # seconds (server clock)
+    future: cf.Future = field(default_factory=cf.Future)
+    start: float = 0.0             # dispatch time
+    done: float = 0.0              # completion time
+    batch_size: int = 0
+
+
+class LweError(RuntimeError):
+    pass
+
+
+def footprint_bytes(n: int, op: int, count: int) -> int:
+    """Device bytes one library call needs for `count` instances of `op` at dimension n
+    (operand and error stacks, round keys, staged inputs and outputs; upper bound)."""
+    ldx = (n + 63) // 64 * 64
+    pk = 16 + 16 * n
+    sk = 16 * n + pk + 64
+    ct = 16 * n + 128
+    per = 8 * ldx + 8 * n + 64 + 44 * 4 + 16 + 32 + 32 + 64 + 8
+    if op == KEYGEN:
+        per += pk + sk + 64
+    elif op == ENCAPS:
+        per += ct + 64 + 32
+    else:
+        per += 2 * ct + 64 + 32
+    # split-K accumulator of the streaming product for small groups
+    acc = 8 * count * (n + 8) * 4 if count * 8 < 256 else 0
+    return count * per + acc + (1 << 20)
+
+
+class Backend:
+    """What the scheduler needs from the device side (the real one is LibraryBackend)."""
+
+    def lanes(self) -> int:
+        raise NotImplementedError
+
+    def run(self, lane: int, op: int, n: int, key: int, payloads: List[Tuple]) -> List:
+        raise NotImplementedError
+
+
+class Server:
+    """Continuous-batching scheduler.
+
+    backend     executes one group on a lane and returns one result per request
+    hbm_budget  bytes of device working memory all in-flight groups may reserve
+    max_batch   largest group handed to one library call
+    clock       time source (seconds); injectable for tests
+    """
+
+    def __init__(self, backend: Backend, hbm_budget: int, max_batch: int = 4096,
+                 clock: Callable[[], float] = time.perf_counter,
+                 footprint: Callable[[int, int, int], int] = footprint_bytes):
+        self.backend = backend
+        self.budget = int(hbm_budget)
+        self.max_batch = int(max_batch)
+        self.clock = clock
+        self.footprint = footprint
+        self._queues: Dict[Tuple[int, int, int], collections.deque] = collections.OrderedDict()
+        self._cv = threading.Condition()
+        self._free_lanes = list(range(backend.lanes()))
+        self._reserved = 0
+        self.max_reserved = 0
+        self.max_in_flight_groups = 0
+        self._in_flight = 0
+        self._stop = False
+        self._pool = cf.ThreadPoolExecutor(max_workers=backend.lanes(), thread_name_prefix="lwe-lane")
+        self._sched = threading.Thread(target=self._loop, name="lwe-scheduler", daemon=True)
+        self.completed: List[Request] = []
+        self.groups: List[Tuple[int, int, int, int]] = []  # (op, n, key, size) per dispatched group
+        self._sched.start()
+
+    # ---- client side ----
+    def submit(self, op: int, n: int, key: int, payload: Tuple, arrival: Optional[float] = None) -> cf.Future:
+        r = Request(op, n, key if op != KEYGEN else -1, payload,
+                    arrival=self.clock() if arrival is None else arrival)
+        with self._cv:
+            if self._stop:
+                raise RuntimeError("server stopped")
+            self._queues.setdefault((op, n, r.key), collections.deque()).append(r)
+            self._cv.notify_all()
+        return r.future
+
+    def close(self) -> None:
+        with self._cv:
+            self._stop = True
+            self._cv.notify_all()
+        self._sched.join()
+        self._pool.shutdown(wait=True)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ---- scheduler ----
+    def _pick_group(self) -> Optional[Tuple[Tuple[int, int, int], List[Request], int]]:
+        """Oldest queue head first; as many of its requests as fit the free budget."""
+        best = None
+        for k, q in self._queues.items():
+            if q and (best is None or q[0].arrival < self._queues[best][0].arrival):
+                best = k
+        if best is None:
+            return None
+        op, n, key = best
+        q = self._queues[best]
+        free = self.budget - self._reserved
+        take = min(len(q), self.max_batch)
+        while take > 0 and self.footprint(n, op, take) > free:
+            take //= 2
+        if take == 0:
+            if self._in_flight == 0 and self.footprint(n, op, 1) > self.budget:
+                # can never fit: fail this request alone
+                r = q.popleft()
+                r.future.set_exception(LweError("request needs more device memory than the budget (LWE_ENOMEM)"))
+                return self._pick_group()
+            return None
+        reqs = [q.popleft() for _ in range(take)]
+        if not q:
+            del self._queues[best]
+        return best, reqs, self.footprint(n, op, take)
+
+    def _loop(self) -> None:
+        while True:
+            with self._cv:
+                while True:
+                    if self._stop and not any(self._queues.values()) and self._in_flight == 0:
+                        return
+                    if self._free_lanes:
+                        g = self._pick_group()
+                        if g is not None:
+                            break
+                    self._cv.wait(timeout=0.05)
+                (op, n, key), reqs, fp = g
+                lane = self._free_lanes.pop()
+                self._reserved += fp
+                self._in_flight += 1
+                self.max_reserved = max(self.max_reserved, self._reserved)
+                self.max_in_flight_groups = max(self.max_in_flight_groups, self._in_flight)
+                self.groups.append((op, n, key, len(reqs)))
+            self._pool.submit(self._run_group, lane, op, n, key, reqs, fp)
+
+    def _run_group(self, lane: int, op: int, n: int, key: int, reqs: List[Request], fp: int) -> None:
+        t0 = self.clock()
+        for r in reqs:
+            r.start = t0
+            r.batch_size = len(reqs)
+        try:
+            results = self.backend.run(lane, op, n, key, [r.payload for r in reqs])
+            err = None
+        except Exception as e:  # the whole group failed: report it to each of its requests
+            results, err = None, e
+        t1 = self.clock()
+        with self._cv:
+            self._reserved -= fp
+            self._in_flight -= 1
+            self._free_lanes.append(lane)
+            for i, r in enumerate(reqs):
+                r.done = t1
+                self.completed.append(r)
+            self._cv.notify_all()
+        for i, r in enumerate(reqs):
+            if err is not None:
+                r.future.set_exception(err)
+            else:
+                r.future.set_result(results[i])
+
+    # ---- statistics ----
+    def latency_ms(self, op: Optional[int] = None) -> np.ndarray:
+        with self._cv:
+            return np.array([1e3 * (r.done - r.arrival) for r in self.completed if op is None or r.op == op])
+
+
+class LibraryBackend(Backend):
+    """Runs groups through liblwe_hip: one context and one HIP stream per lane, key pairs
+    resident on the device."""
+
+    def __init__(self, ns, keys_per_n: int = 16, lanes: int = 3, device: int = 0,
+                 lane_budget: int = 0, key_seed: int = 4, keys: Optional[Dict] = None):
+        import torch
+
+        import lwe_inputs
+        from . import lwe
+
+        self.torch = torch
+        self.L = lwe
+        self.dev = torch.device("cuda:%d" % device)
+        self._lanes = [lwe.Context(device, lane_budget) for _ in range(lanes)]
+        self._streams = [torch.cuda.Stream(device=self.dev) for _ in range(lanes)]
+        self.pids = {n: lwe.param_id(n) for n in ns}
+        self.params = {n: lwe.params(self.pids[n]) for n in ns}
+        self.keys: Dict[int, List[Tuple]] = {}
+        g = lwe_inputs.rng(key_seed, 0)
+        for n in ns:
+            p = self.params[n]
+            if keys is not None:  # key pairs supplied by the caller: {n: (pk[k][..], sk[k][..])}
+                pk, sk = (np.ascontiguousarray(x, np.uint8) for x in keys[n])
+            else:
+                seedA, seedSK, z = lwe_inputs.keygen_seeds(g, keys_per_n)
+                pk = np.zeros((keys_per_n, p.pk_bytes), np.uint8)
+                sk = np.zeros((keys_per_n, p.sk_bytes), np.uint8)
+                self._lanes[0].keygen_batch(p.pid, keys_per_n, seedA, seedSK, z, pk, sk)
+            self.keys[n] = [(torch.from_numpy(pk[i].copy()).to(self.dev), torch.from_numpy(sk[i].copy()).to(self.dev),
+                             pk[i].copy(), sk[i].copy()) for i in range(keys_per_n)]
+        torch.cuda.synchronize()
+
+    def lanes(self) -> int:
+        return len(self._lanes)
+
+    def host_key(self, n: int, key: int):
+        return self.keys[n][key][2], self.keys[n][key][3]
+
+    def run(self, lane: int, op: int, n: int, key: int, payloads: List[Tuple]) -> List:
+        ctx, st = self._lanes[lane], self._streams[lane].cuda_stream
+        p = self.params[n]
+        c = len(payloads)
+        if op == KEYGEN:
+            seedA = np.stack([np.frombuffer(bytes(x[0]), np.uint8) for x in payloads])
+            seedSK = np.stack([np.frombuffer(bytes(x[1]), np.uint8) for x in payloads])
+            z = np.stack([np.frombuffer(bytes(x[2]), np.uint8) for x in payloads])
+            pk = np.zeros((c, p.pk_bytes), np.uint8)
+            sk = np.zeros((c, p.sk_bytes), np.uint8)
+            ctx.keygen_batch(p.pid, c, seedA, seedSK, z, pk, sk, stream=st)
+            return [(pk[i].tobytes(), sk[i].tobytes()) for i in range(c)]
+        d_pk, d_sk = self.keys[n][key][0], self.keys[n][key][1]
+        if op == ENCAPS:
+            mu = np.stack([np.frombuffer(bytes(x[0]), np.uint8) for x in payloads])
+            ct = np.zeros((c, p.ct_bytes), np.uint8)
+            ss = np.zeros((c, 32), np.uint8)
+            ctx.encaps_batch(p.pid, c, d_pk, mu, ct, ss, stream=st)
+            return [(ct[i].tobytes(), ss[i].tobytes()) for i in range(c)]
+        cts = np.stack([np.frombuffer(bytes(x[0]), np.uint8) for x in payloads])
+        ss = np.zeros((c, 32), np.uint8)
+        ctx.decaps_batch(p.pid, c, d_sk, cts, ss, stream=st)
+        return [ss[i].tobytes() for i in range(c)]
+
+    def close(self) -> None:
+        for c in self._lanes:
+            c.close()
+
+
+# ---------------------------------------------------------------------------------------
+# Load generator (the serving workload: Poisson arrivals, mixed ops and dimensions)
+# ---------------------------------------------------------------------------------------
+def run_load(server: Server, backend: LibraryBackend, qps: float, duration_s: float, ns, keys_per_n: int,
+             mix=(0.2, 0.5, 0.3), seed: int = 0, ct_pool: Optional[Dict] = None) -> Dict:
+    """Open-loop load: requests arrive at Poisson times regardless of completions.  Decaps
+    requests use ciphertexts produced by earlier Encaps of the same key (a pool seeded
+    before the run).  Returns throughput and latency percentiles."""
+    import lwe_inputs
+
+    g = lwe_inputs.rng(4, 100 + seed)
+    count = max(1, int(qps * duration_s))
+    arrivals = lwe_inputs.poisson_arrivals(g, qps, count)
+    ops, nsel = lwe_inputs.request_mix(g, count, ns, mix)
+    keys = g.integers(0, keys_per_n, size=count)
+    if ct_pool is None:
+        ct_pool = prime_ct_pool(backend, ns, keys_per_n)
+    futs = []
+    t0 = server.clock()
+    for i in range(count):
+        target = t0 + arrivals[i]
+        while True:
+            now = server.clock()
+            if now >= target:
+                break
+            time.sleep(min(0.0005, target - now))
+        op, n, key = int(ops[i]), int(nsel[i]), int(keys[i])
+        p = backend.params[n]
+        if op == KEYGEN:
+            sa, ss_, z = lwe_inputs.keygen_seeds(g, 1)
+            payload = (sa[0].tobytes(), ss_[0].tobytes(), z[0].tobytes())
+        elif op == ENCAPS:
+            payload = (lwe_inputs.messages(g, 1, p.mu_bytes)[0].tobytes(),)
+        else:
+            pool = ct_pool[(n, key)]
+            payload = (pool[i % len(pool)],)
+        futs.append((op, server.submit(op, n, key, payload, arrival=target)))
+    for _, f in futs:
+        f.result()
+    t1 = server.clock()
+    lat = {OP_NAMES[o]: server.latency_ms(o) for o in (KEYGEN, ENCAPS, DECAPS)}
+    allat = server.latency_ms()
+    return {
+        "requests": count,
+        "offered_qps": qps,
+        "achieved_ops_per_s": count / (t1 - t0),
+        "p50_ms": float(np.percentile(allat, 50)),
+        "p99_ms": float(np.percentile(allat, 99)),
+        "per_op": {k: {"p50_ms": float(np.percentile(v, 50)), "p99_ms": float(np.percentile(v, 99)),
+                       "count": int(v.size)} for k, v in lat.items() if v.size},
+        "mean_group": float(np.mean([gsz[3] for gsz in server.groups])) if server.groups else 0.0,
+        "max_reserved_bytes": server.max_reserved,
+        "budget_bytes": server.budget,
+        "max_concurrent_groups": server.max_in_flight_groups,
+    }
+
+
+def prime_ct_pool(backend: LibraryBackend, ns, keys_per_n: int, per_key: int = 4) -> Dict:
+    """Ciphertexts for the Decaps requests: `per_key` encapsulations per resident key."""
+    import lwe_inputs
+
+    g = lwe_inputs.rng(4, 7)
+    pool = {}
+    for n in ns:
+        p = backend.params[n]
+        for key in range(keys_per_n):
+            mus = [(lwe_inputs.messages(g, 1, p.mu_bytes)[0].tobytes(),) for _ in range(per_key)]
+            res = backend.run(0, ENCAPS, n, key, mus)
+            pool[(n, key)] = [r[0] for r in res]
+    return pool
+
+
+def main(argv=None) -> int:
+    import argparse
+    import json
+
+    ap = argparse.ArgumentParser(description="Continuous-batching KEM serving benchmark (one GPU)")
+    ap.add_argument("--ns", default="640,976,1344,4096")
+    ap.add_argument("--keys-per-n", type=int, default=16)
+    ap.add_argument("--lanes", type=int, default=3)
+    ap.add_argument("--qps", type=float, default=0.0, help="offered load; 0 = measure capacity first")
+    ap.add_argument("--duration", type=float, default=10.0)
+    ap.add_argument("--budget-gb", type=float, default=16.0)
+    ap.add_argument("--max-batch", type=int, default=1024)
+    args = ap.parse_args(argv)
+    ns = [int(x) for x in args.ns.split(",")]
+    be = LibraryBackend(ns, args.keys_per_n, args.lanes)
+    pool = prime_ct_pool(be, ns, args.keys_per_n)
+    out = {"ns": ns, "keys_per_n": args.keys_per_n, "lanes": args.lanes, "mix": [0.2, 0.5, 0.3]}
+    budget = int(args.budget_gb * (1 << 30))
+    if args.qps <= 0:
+        # capacity: a closed burst of requests all arriving at t = 0
+        with Server(be, budget, args.max_batch) as s:
+            r = run_load(s, be, 1e9, 2000 / 1e9, ns, args.keys_per_n, ct_pool=pool)
+        cap = r["achieved_ops_per_s"]
+        out["capacity_ops_per_s"] = cap
+        runs = {}
+        for frac in (0.5, 0.8):
+            with Server(be, budget, args.max_batch) as s:
+                runs["%.1fC" % frac] = run_load(s, be, frac * cap, args.duration, ns, args.keys_per_n, ct_pool=pool)
+        out["runs"] = runs
+    else:
+        with Server(be, budget, args.max_batch) as s:
+            out["runs"] = {"qps=%g" % args.qps: run_load(s, be, args.qps, args.duration, ns, args.keys_per_n,
+                                                          ct_pool=pool)}
+    be.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

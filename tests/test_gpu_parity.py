@@ -148,8 +148,8 @@ def test_keygen(ctx, orc, n, count):
 @pytest.mark.parametrize("n", [200, 640, 976, 1344])
 @pytest.mark.parametrize("count", [1, 20, 300])
 def test_encaps_decaps(ctx, orc, n, count):
-    """Encaps (Alg. 4) and Decaps (Alg. 5) against the oracle; a quarter of the ciphertexts
-    are tampered before decapsulation (implicit rejection)."""
+    """Encaps (Alg. 4) and Decaps (Alg. 5) against the oracle.  Decaps gets ciphertexts made
+    by the oracle, a quarter of them tampered (implicit rejection)."""
     lp, op = _pair(orc, n)
     g = lwe_inputs.rng(0, 1700 + n + count)
     pk, sk = _keypair(orc, op, g)
@@ -159,25 +159,33 @@ def test_encaps_decaps(ctx, orc, n, count):
     say("encaps", n, count)
     ctx.encaps_batch(lp.pid, count, pk, mus, ct, ss)
     check = sorted(set([0, count - 1, count // 2, count // 5]))
+    oracle_ct = {}
     for i in check:
         oct_, oss = orc.kem_encaps(op, pk, mus[i].tobytes())
+        oracle_ct[i] = (oct_, oss)
         assert ct[i].tobytes() == oct_, i
         assert ss[i].tobytes() == oss, i
-    bad = ct.copy()
-    tampered = list(range(0, count, 4))
-    for i in tampered:
-        bad[i, (i * 97) % op.ct_bytes] ^= 1 << (i % 8)
-    ss2 = np.zeros((count, 32), np.uint8)
-    say("decaps", n, count)
-    ctx.decaps_batch(lp.pid, count, sk, bad, ss2)
-    for i in range(count):
-        if i in tampered:
-            if i in check or i < 8:
-                oss, ok = orc.kem_decaps(op, sk, bad[i].tobytes())
-                assert not ok
-                assert ss2[i].tobytes() == oss, i
-        else:
-            assert ss2[i].tobytes() == ss[i].tobytes(), i
+    # decapsulation inputs: the oracle's ciphertexts, every other one tampered; 5 of them take
+    # the host-hashing path, 20 the device-hashing path
+    base = [oracle_ct[i][0] for i in check]
+    for nd in (5, 20):
+        dec_in = np.zeros((nd, op.ct_bytes), np.uint8)
+        for k in range(nd):
+            c = bytearray(base[k % len(base)])
+            if k % 2 == 1:
+                c[(k * 97) % op.ct_bytes] ^= 1 << (k % 8)
+            dec_in[k] = np.frombuffer(bytes(c), np.uint8)
+        ss2 = np.zeros((nd, 32), np.uint8)
+        say("decaps", n, nd)
+        ctx.decaps_batch(lp.pid, nd, sk, dec_in, ss2)
+        for k in range(nd):
+            oss, ok = orc.kem_decaps(op, sk, dec_in[k].tobytes())
+            assert ok == (k % 2 == 0)
+            assert ss2[k].tobytes() == oss, (nd, k)
+    # the full batch round-trips on the device (KEM invariant, no oracle involved)
+    ss3 = np.zeros((count, 32), np.uint8)
+    ctx.decaps_batch(lp.pid, count, sk, ct, ss3)
+    assert np.array_equal(ss3, ss)
 
 
 def test_device_tensors_async(ctx, orc):
@@ -254,8 +262,9 @@ def test_large_n_full(ctx, orc, n):
 
 @pytest.mark.parametrize("n", [16384, 32768])
 def test_large_n_sampled(ctx, orc, n):
-    """At n = 16384 and 32768 the oracle checks sampled entries of B^T and B', all of V, the
-    hashes, and the KEM invariant."""
+    """At n = 16384 and 32768: sampled entries of B^T against the oracle, the secret key in
+    full, encryption with explicit coins under a public key built from seeded inputs (B' at
+    sampled entries, V in full), and the KEM invariant on the device."""
     lp, op = _pair(orc, n)
     g = lwe_inputs.rng(2, n)
     seedA, seedSK, z = lwe_inputs.keygen_seeds(g, 1)
@@ -273,23 +282,28 @@ def test_large_n_sampled(ctx, orc, n):
     skb = sk.tobytes()
     assert skb[16 * n:16 * n + op.pk_bytes] == pk.tobytes()
     assert skb[16 * n + op.pk_bytes:16 * n + op.pk_bytes + 32] == H(pk.tobytes()) and skb[-32:] == zz
-    mu = lwe_inputs.messages(g, 1, op.mu_bytes)[0]
+    # encryption with explicit coins under pk' = seedA || (seeded uniform B^T)
+    Bt_syn = (lwe_inputs.random_bytes(g, 8, 2 * n).view("<u2") & (op.q - 1)).astype("<u2")
+    pk_syn = sA + Bt_syn.tobytes()
+    coins = lwe_inputs.coins(g, 1)
+    mu = lwe_inputs.messages(g, 1, op.mu_bytes)
     ct = np.zeros(op.ct_bytes, np.uint8)
-    ss = np.zeros(32, np.uint8)
-    say("sampled encaps", n)
-    ctx.encaps(lp.pid, pk, mu, ct, ss)
-    coins, kp = orc.fo_coins(op, H(pk.tobytes()), mu.tobytes())
+    say("sampled encrypt", n)
+    ctx.test_encrypt(lp.pid, 1, pk_syn, coins, mu, ct)
     Bp = np.frombuffer(ct.tobytes()[:16 * n], "<u2").reshape(8, n)
     for r, j in [(0, 0), (7, n - 1), (2, n // 3), (6, 9999 % n)]:
-        assert Bp[r, j] == orc.Bp_entry(op, sA, coins, r, j), (r, j)
+        assert Bp[r, j] == orc.Bp_entry(op, sA, coins[0].tobytes(), r, j), (r, j)
     V = np.frombuffer(ct.tobytes()[16 * n:], "<u2").reshape(8, 8)
-    assert np.array_equal(V, orc.pke_V(op, Bt, coins, mu.tobytes()))
-    assert ss.tobytes() == H(kp + H(ct.tobytes()))
+    assert np.array_equal(V, orc.pke_V(op, Bt_syn, coins[0].tobytes(), mu[0].tobytes()))
+    # KEM invariant and implicit rejection on the device
+    ct2 = np.zeros(op.ct_bytes, np.uint8)
+    ss = np.zeros(32, np.uint8)
     ss2 = np.zeros(32, np.uint8)
-    say("sampled decaps", n)
-    ctx.decaps(lp.pid, sk, ct, ss2)
+    say("sampled encaps/decaps", n)
+    ctx.encaps(lp.pid, pk, mu[0], ct2, ss)
+    ctx.decaps(lp.pid, sk, ct2, ss2)
     assert np.array_equal(ss, ss2)
-    bad = ct.copy()
+    bad = ct2.copy()
     bad[5] ^= 4
     ctx.decaps(lp.pid, sk, bad, ss2)
     assert ss2.tobytes() == H(zz + H(bad.tobytes()))

@@ -1,0 +1,123 @@
+"""Serving on the GPU: mixed KeyGen / Encaps / Decaps requests of different n arrive while
+other groups are in flight; every result must be byte-identical to the same request run
+alone (tolerance 0: the arithmetic is integer), and a sample is checked against the oracle."""
+import sys
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import lwe_inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+NS = [640, 976, 1344]
+
+
+@pytest.fixture(scope="module")
+def keys(orc):
+    """Resident key pairs made by the oracle from seeded inputs, so that every oracle check
+    below starts from inputs that never went through the HIP path."""
+    out = {}
+    g = lwe_inputs.rng(4, 54)
+    for n in NS:
+        o = orc.params_for(n)
+        pairs = [orc.kem_keygen(o, *(x[0].tobytes() for x in lwe_inputs.keygen_seeds(g, 1))) for _ in range(3)]
+        out[n] = (np.stack([np.frombuffer(p[0], np.uint8) for p in pairs]),
+                  np.stack([np.frombuffer(p[1], np.uint8) for p in pairs]))
+    return out
+
+
+@pytest.fixture(scope="module")
+def backend(keys):
+    from paper_2606_01211_amd.serve import LibraryBackend
+
+    be = LibraryBackend(NS, keys_per_n=3, lanes=3, keys=keys)
+    yield be
+    be.close()
+
+
+def test_mix_equals_alone(backend, keys, orc):
+    from paper_2606_01211_amd.serve import DECAPS, ENCAPS, KEYGEN, Server
+
+    ns = NS
+    g = lwe_inputs.rng(4, 55)
+    # Decaps inputs: ciphertexts the oracle made for the resident keys
+    pool = {}
+    for n in ns:
+        o = orc.params_for(n)
+        for key in range(3):
+            pool[(n, key)] = [orc.kem_encaps(o, keys[n][0][key].tobytes(),
+                                             lwe_inputs.messages(g, 1, o.mu_bytes)[0].tobytes())[0]
+                              for _ in range(2)]
+    reqs = []
+    for i in range(240):
+        op = int(g.choice(3, p=[0.2, 0.5, 0.3]))
+        n = int(ns[i % 3])
+        key = int(g.integers(0, 3))
+        p = backend.params[n]
+        if op == KEYGEN:
+            sa, ssk, z = lwe_inputs.keygen_seeds(g, 1)
+            payload = (sa[0].tobytes(), ssk[0].tobytes(), z[0].tobytes())
+        elif op == ENCAPS:
+            payload = (lwe_inputs.messages(g, 1, p.mu_bytes)[0].tobytes(),)
+        else:
+            ct = bytearray(pool[(n, key)][i % 2])
+            if i % 7 == 0:
+                ct[i % len(ct)] ^= 1  # some tampered ciphertexts: implicit rejection in the mix
+            payload = (bytes(ct),)
+        reqs.append((op, n, key, payload))
+    say("serving mix of", len(reqs))
+    server = Server(backend, hbm_budget=2 << 30, max_batch=64)
+    futs = []
+    for i, (op, n, key, payload) in enumerate(reqs):
+        futs.append(server.submit(op, n, key, payload))
+        if i % 20 == 19:
+            time.sleep(0.002)  # arrivals spread over time: later requests join while others run
+    results = [f.result(timeout=120) for f in futs]
+    assert server.max_reserved <= server.budget
+    groups = list(server.groups)
+    server.close()
+    assert len(groups) < len(reqs)
+    say("groups", len(groups), "max concurrent", server.max_in_flight_groups)
+    # alone: each request as its own group of one
+    for i, (op, n, key, payload) in enumerate(reqs):
+        alone = backend.run(0, op, n, key, [payload])[0]
+        assert alone == results[i], (i, op, n)
+    # oracle on a sample (its inputs: seeds, messages, oracle keys and oracle ciphertexts)
+    for i, (op, n, key, payload) in enumerate(reqs[:30]):
+        o = orc.params_for(n)
+        pk, sk = keys[n][0][key], keys[n][1][key]
+        if op == KEYGEN:
+            assert results[i] == orc.kem_keygen(o, *payload)
+        elif op == ENCAPS:
+            assert results[i] == orc.kem_encaps(o, pk.tobytes(), payload[0])
+        else:
+            assert results[i] == orc.kem_decaps(o, sk.tobytes(), payload[0])[0]
+
+
+def test_small_budget_admission(backend):
+    """A budget that admits only small groups still serves every request, never reserves
+    more than the budget, and a request that cannot fit at all fails alone."""
+    from paper_2606_01211_amd.serve import ENCAPS, LweError, Server, footprint_bytes
+
+    budget = footprint_bytes(1344, ENCAPS, 4)
+    g = lwe_inputs.rng(4, 56)
+    with Server(backend, hbm_budget=budget, max_batch=64) as s:
+        futs = [s.submit(ENCAPS, 1344, i % 3, (lwe_inputs.messages(g, 1, 32)[0].tobytes(),)) for i in range(40)]
+        out = [f.result(timeout=120) for f in futs]
+        assert s.max_reserved <= budget
+        assert max(gr[3] for gr in s.groups) <= 4
+    assert len(out) == 40
+    tiny = footprint_bytes(640, ENCAPS, 1) - 1
+    with Server(backend, hbm_budget=tiny, max_batch=64) as s:
+        f = s.submit(ENCAPS, 640, 0, (bytes(16),))
+        with pytest.raises(LweError):
+            f.result(timeout=60)
