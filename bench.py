@@ -53,6 +53,9 @@ def parse():
     ap.add_argument("--n", type=int, default=1344)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--plain", type=int, default=300, help="plain encaps and decaps calls timed one by one")
+    ap.add_argument("--streams", type=int, default=2,
+                    help="independent steps in flight (one library context and HIP stream each); the "
+                         "serial rate (one stream) is always measured too")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="budget of the CPU oracle leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -92,47 +95,79 @@ def main():
     p = L.params(pid)
     B = args.batch
     K, W = args.steps, args.warmup
-    ctx = L.Context(0)
+    S = max(1, args.streams)
+    ctxs = [L.Context(0) for _ in range(S)]
+    streams = [torch.cuda.Stream(device=dev) for _ in range(S)]
+    ctx = ctxs[0]
 
     g = lwe_inputs.rng(3, 0)
-    seedA, seedSK, z = lwe_inputs.keygen_seeds(g, W + K)
+    seedA, seedSK, z = lwe_inputs.keygen_seeds(g, W + 2 * K)
     mus = lwe_inputs.messages(g, B, p.mu_bytes)
     d_mu = torch.from_numpy(mus).to(dev)
-    d_pk = torch.empty(p.pk_bytes, dtype=torch.uint8, device=dev)
-    d_sk = torch.empty(p.sk_bytes, dtype=torch.uint8, device=dev)
-    d_ct = torch.empty((B, p.ct_bytes), dtype=torch.uint8, device=dev)
-    d_ss = torch.empty((B, 32), dtype=torch.uint8, device=dev)
-    d_ss2 = torch.empty((B, 32), dtype=torch.uint8, device=dev)
+    bufs = []
+    for _ in range(S):
+        bufs.append({
+            "pk": torch.empty(p.pk_bytes, dtype=torch.uint8, device=dev),
+            "sk": torch.empty(p.sk_bytes, dtype=torch.uint8, device=dev),
+            "ct": torch.empty((B, p.ct_bytes), dtype=torch.uint8, device=dev),
+            "ss": torch.empty((B, 32), dtype=torch.uint8, device=dev),
+            "ss2": torch.empty((B, 32), dtype=torch.uint8, device=dev),
+        })
+    torch.cuda.synchronize()
 
-    def step(i):
-        ctx.keygen(pid, seedA[i], seedSK[i], z[i], d_pk, d_sk)
-        ctx.encaps_batch(pid, B, d_pk, d_mu, d_ct, d_ss)
-        ctx.decaps_batch(pid, B, d_sk, d_ct, d_ss2)
+    def step(i, lane):
+        c, st, bf = ctxs[lane], streams[lane], bufs[lane]
+        with torch.cuda.stream(st):
+            c.keygen(pid, seedA[i], seedSK[i], z[i], bf["pk"], bf["sk"])
+            c.encaps_batch(pid, B, bf["pk"], d_mu, bf["ct"], bf["ss"])
+            c.decaps_batch(pid, B, bf["sk"], bf["ct"], bf["ss2"])
 
     for i in range(W):
-        step(i)
+        for lane in range(S):
+            step(i, lane)
     torch.cuda.synchronize()
     print("warmup done", file=sys.stderr, flush=True)
 
+    def timed(lanes, first_seed):
+        """K steps spread round-robin over `lanes` streams; returns wall seconds, per-step
+        device latencies (ms) and the merged kernel profile."""
+        for c in ctxs:
+            c.prof_reset()
+            c.prof_enable(True)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(K):
+            lane = i % lanes
+            with torch.cuda.stream(streams[lane]):
+                ev[i][0].record()
+            step(first_seed + i, lane)
+            with torch.cuda.stream(streams[lane]):
+                ev[i][1].record()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = {}
+        for c in ctxs:
+            for k, (cnt, ms) in c.prof_read().items():
+                a = prof.setdefault(k, [0, 0.0])
+                a[0] += cnt
+                a[1] += ms
+            c.prof_enable(False)
+        return t1 - t0, [e0.elapsed_time(e1) for e0, e1 in ev], prof
+
     # ---------------- batched, timed ----------------
-    ctx.prof_reset()
-    ctx.prof_enable(True)
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    evs[0].record()
-    for i in range(K):
-        step(W + i)
-        evs[i + 1].record()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = ctx.prof_read()
-    ctx.prof_enable(False)
-    wall = t1 - t0
+    wall1, step_ms1, prof1 = timed(1, W)
+    serial_value = K * B / wall1
+    if S > 1:
+        wall, step_ms, prof = timed(S, W + K)
+    else:
+        wall, step_ms, prof = wall1, step_ms1, prof1
     value = K * B / wall
-    step_ms = [evs[i].elapsed_time(evs[i + 1]) for i in range(K)]
-    device_agree = bool(torch.equal(d_ss, d_ss2))
-    print("batched: %.1f encaps+decaps/s, %.3f ms/step" % (value, 1e3 * wall / K), file=sys.stderr, flush=True)
+    device_agree = all(bool(torch.equal(bf["ss"], bf["ss2"])) for bf in bufs)
+    d_pk, d_sk, d_ct, d_ss = bufs[0]["pk"], bufs[0]["sk"], bufs[0]["ct"], bufs[0]["ss"]
+    last_seed = W + K + (K - 1) - ((K - 1) % S) if S > 1 else W + K - 1  # last step run on lane 0
+    print("batched: %.1f encaps+decaps/s (%d streams), serial %.1f, %.3f ms/step" %
+          (value, S, serial_value, 1e3 * wall / K), file=sys.stderr, flush=True)
 
     # ---------------- plain: one instance per call ----------------
     P = args.plain
@@ -160,7 +195,7 @@ def main():
     # ---------------- roofline of the dominant kernel ----------------
     n = p.n
     M = 8 * B
-    kern = {k: {"launches": v[0], "total_ms": v[1], "avg_us": 1e3 * v[1] / v[0]} for k, v in prof.items()}
+    kern = {k: {"launches": v[0], "total_ms": v[1], "avg_us": 1e3 * v[1] / v[0]} for k, v in prof1.items()}
     dominant = max(kern, key=lambda k: kern[k]["total_ms"])
     d = kern[dominant]
     avg_s = d["avg_us"] * 1e-6
@@ -190,7 +225,7 @@ def main():
 
         op = oracle.params_for(n)
         # the oracle starts from the same seeds as the GPU, never from GPU outputs
-        i_last = W + K - 1
+        i_last = last_seed
         ta = time.perf_counter()
         opk, osk = oracle.kem_keygen(op, seedA[i_last].tobytes(), seedSK[i_last].tobytes(), z[i_last].tobytes())
         bit_exact &= opk == d_pk.cpu().numpy().tobytes() and osk == d_sk.cpu().numpy().tobytes()
@@ -226,6 +261,9 @@ def main():
                    "nbar": 8, "mbar": 8, "step": "keygen + encaps_batch + decaps_batch"},
         "bit_exact": bit_exact,
         "batch_latency_ms": {"p50": pct(step_ms, 50), "p99": pct(step_ms, 99)},
+        "streams": S,
+        "serial": {"value": serial_value, "ms_per_step": 1e3 * wall1 / K,
+                   "batch_latency_ms": {"p50": pct(step_ms1, 50), "p99": pct(step_ms1, 99)}},
         "plain": {"value": plain_rate, "unit": "encaps+decaps/s",
                   "encaps_ms": {"p50": pct(enc_ms, 50), "p99": pct(enc_ms, 99)},
                   "decaps_ms": {"p50": pct(dec_ms, 50), "p99": pct(dec_ms, 99)}, "calls": len(enc_ms)},
@@ -234,7 +272,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
-    ctx.close()
+    for c in ctxs:
+        c.close()
     print(json.dumps(out), flush=True)
     return 0
 

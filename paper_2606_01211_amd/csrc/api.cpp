@@ -299,7 +299,8 @@ int run_product(lwe_ctx* c, int pid, const Params& p, ProdArgs a, bool trans, hi
         }
     }
     const int RG = tu.row_groups ? (int)tu.row_groups : (CG >= 3 ? 2 : 4);
-    const int max_rows = (int)(((160 * 1024 - 4096) / (32 * CG)) / 64 * 64);
+    // longest K chunk whose padded strip fits LDS (a multiple of three 64-row steps)
+    const int max_rows = (int)(((160 * 1024 - 4096) / (32 * CG)) / 192 * 192);
     a.kc_len = std::min(ksteps * 64, max_rows);
     a.n_kc = (p.n + a.kc_len - 1) / a.kc_len;
     a.n_jt = (a.ncols + 16 * CG - 1) / (16 * CG);

@@ -9,6 +9,8 @@
 //    signed 8-bit limbs x = lo + 256 hi (mod 2^16), both limbs are multiplied against the
 //    small int8 matrix with int32 accumulation, and lo + 256 hi is reduced mod 2^logq.
 //  * SHA3-256 sponges for the Fujisaki-Okamoto transform (Alg. 4-5).
+#include <type_traits>
+
 #include "lwe_internal.h"
 
 namespace lwe {
@@ -36,10 +38,38 @@ __device__ __forceinline__ uint32_t x3(uint32_t a, uint32_t b, uint32_t c) {
   return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
 }
 
+// Byte address of T-table entry (byte BYTE of x): one SDWA shift selects the byte and
+// scales it by four, where the plain form takes an extract and a shift-add.
+template <int BYTE>
+__device__ __forceinline__ uint32_t tab_addr(uint32_t x) {
+  uint32_t r;
+  if constexpr (BYTE == 0)
+    asm("v_lshlrev_b32_sdwa %0, 2, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0"
+        : "=v"(r) : "v"(x));
+  else if constexpr (BYTE == 1)
+    asm("v_lshlrev_b32_sdwa %0, 2, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_1"
+        : "=v"(r) : "v"(x));
+  else if constexpr (BYTE == 2)
+    asm("v_lshlrev_b32_sdwa %0, 2, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_2"
+        : "=v"(r) : "v"(x));
+  else
+    asm("v_lshlrev_b32_sdwa %0, 2, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_3"
+        : "=v"(r) : "v"(x));
+  return r;
+}
+
+// Entry of table TAB (0..3, the byte rotations of T0) at byte address `addr`; the table
+// offset folds into the LDS instruction's immediate.
+template <int TAB>
+__device__ __forceinline__ uint32_t tab(const uint32_t* __restrict__ T, uint32_t addr) {
+  return *(const uint32_t*)((const char*)T + addr + 1024 * TAB);
+}
+
 // Encrypts the CTR counter block of domain `dom` (as its little-endian word) and block
-// index b: the 128-bit big-endian integer dom * 2^96 + b.  Per round and column: four
-// table lookups (one shifted-byte address each) folded with the round key by two 3-input
-// XORs.
+// index b: the 128-bit big-endian integer dom * 2^96 + b, with round keys rk[0..43]
+// (FIPS-197 key expansion) and the T-tables in LDS.  Per round and column: four table
+// lookups (one shifted-byte address each) folded with the round key by two 3-input XORs.
+// o[] receives the keystream block as four little-endian words.
 template <class RK>
 __device__ __forceinline__ void aes_ctr_block(const uint32_t* __restrict__ T, const RK& rk,
                                               uint32_t dom_le, uint64_t b, uint32_t o[4]) {
@@ -49,14 +79,14 @@ __device__ __forceinline__ void aes_ctr_block(const uint32_t* __restrict__ T, co
   uint32_t s3 = bswap32((uint32_t)b) ^ rk[3];
 #pragma unroll
   for (int r = 1; r < 10; ++r) {
-    const uint32_t t0 = x3(x3(T[s0 & 0xff], T[256 + ((s1 >> 8) & 0xff)], T[512 + ((s2 >> 16) & 0xff)]),
-                           T[768 + (s3 >> 24)], rk[4 * r]);
-    const uint32_t t1 = x3(x3(T[s1 & 0xff], T[256 + ((s2 >> 8) & 0xff)], T[512 + ((s3 >> 16) & 0xff)]),
-                           T[768 + (s0 >> 24)], rk[4 * r + 1]);
-    const uint32_t t2 = x3(x3(T[s2 & 0xff], T[256 + ((s3 >> 8) & 0xff)], T[512 + ((s0 >> 16) & 0xff)]),
-                           T[768 + (s1 >> 24)], rk[4 * r + 2]);
-    const uint32_t t3 = x3(x3(T[s3 & 0xff], T[256 + ((s0 >> 8) & 0xff)], T[512 + ((s1 >> 16) & 0xff)]),
-                           T[768 + (s2 >> 24)], rk[4 * r + 3]);
+    const uint32_t t0 = x3(x3(tab<0>(T, tab_addr<0>(s0)), tab<1>(T, tab_addr<1>(s1)), tab<2>(T, tab_addr<2>(s2))),
+                           tab<3>(T, tab_addr<3>(s3)), rk[4 * r]);
+    const uint32_t t1 = x3(x3(tab<0>(T, tab_addr<0>(s1)), tab<1>(T, tab_addr<1>(s2)), tab<2>(T, tab_addr<2>(s3))),
+                           tab<3>(T, tab_addr<3>(s0)), rk[4 * r + 1]);
+    const uint32_t t2 = x3(x3(tab<0>(T, tab_addr<0>(s2)), tab<1>(T, tab_addr<1>(s3)), tab<2>(T, tab_addr<2>(s0))),
+                           tab<3>(T, tab_addr<3>(s1)), rk[4 * r + 2]);
+    const uint32_t t3 = x3(x3(tab<0>(T, tab_addr<0>(s3)), tab<1>(T, tab_addr<1>(s0)), tab<2>(T, tab_addr<2>(s1))),
+                           tab<3>(T, tab_addr<3>(s2)), rk[4 * r + 3]);
     s0 = t0;
     s1 = t1;
     s2 = t2;
@@ -64,17 +94,17 @@ __device__ __forceinline__ void aes_ctr_block(const uint32_t* __restrict__ T, co
   }
   // Final round (no MixColumns): the S-box value of x sits in byte 0 of T2[x], byte 1 of
   // T3[x], byte 2 of T0[x] and byte 3 of T1[x].
-  o[0] = ((T[512 + (s0 & 0xff)] & 0xffu) | (T[768 + ((s1 >> 8) & 0xff)] & 0xff00u) |
-          (T[(s2 >> 16) & 0xff] & 0xff0000u) | (T[256 + (s3 >> 24)] & 0xff000000u)) ^
+  o[0] = ((tab<2>(T, tab_addr<0>(s0)) & 0xffu) | (tab<3>(T, tab_addr<1>(s1)) & 0xff00u) |
+          (tab<0>(T, tab_addr<2>(s2)) & 0xff0000u) | (tab<1>(T, tab_addr<3>(s3)) & 0xff000000u)) ^
          rk[40];
-  o[1] = ((T[512 + (s1 & 0xff)] & 0xffu) | (T[768 + ((s2 >> 8) & 0xff)] & 0xff00u) |
-          (T[(s3 >> 16) & 0xff] & 0xff0000u) | (T[256 + (s0 >> 24)] & 0xff000000u)) ^
+  o[1] = ((tab<2>(T, tab_addr<0>(s1)) & 0xffu) | (tab<3>(T, tab_addr<1>(s2)) & 0xff00u) |
+          (tab<0>(T, tab_addr<2>(s3)) & 0xff0000u) | (tab<1>(T, tab_addr<3>(s0)) & 0xff000000u)) ^
          rk[41];
-  o[2] = ((T[512 + (s2 & 0xff)] & 0xffu) | (T[768 + ((s3 >> 8) & 0xff)] & 0xff00u) |
-          (T[(s0 >> 16) & 0xff] & 0xff0000u) | (T[256 + (s1 >> 24)] & 0xff000000u)) ^
+  o[2] = ((tab<2>(T, tab_addr<0>(s2)) & 0xffu) | (tab<3>(T, tab_addr<1>(s3)) & 0xff00u) |
+          (tab<0>(T, tab_addr<2>(s0)) & 0xff0000u) | (tab<1>(T, tab_addr<3>(s1)) & 0xff000000u)) ^
          rk[42];
-  o[3] = ((T[512 + (s3 & 0xff)] & 0xffu) | (T[768 + ((s0 >> 8) & 0xff)] & 0xff00u) |
-          (T[(s1 >> 16) & 0xff] & 0xff0000u) | (T[256 + (s2 >> 24)] & 0xff000000u)) ^
+  o[3] = ((tab<2>(T, tab_addr<0>(s3)) & 0xffu) | (tab<3>(T, tab_addr<1>(s0)) & 0xff00u) |
+          (tab<0>(T, tab_addr<2>(s1)) & 0xff0000u) | (tab<1>(T, tab_addr<3>(s2)) & 0xff000000u)) ^
          rk[43];
 }
 
@@ -341,10 +371,12 @@ __device__ __forceinline__ void flag_tile(const ProdArgs& a, int row_base, uint3
 // ======================================================================================
 template <int CG, int RG, bool TRANS>
 __global__ void __launch_bounds__(1024) k_prod_stream(ProdArgs a, int ks_per_wave) {
+  // T-tables in static LDS (a compile-time address, so table offsets fold into the LDS
+  // instructions); the reduction / transpose scratch in dynamic LDS.
+  __shared__ uint32_t T[1024];
   extern __shared__ uint32_t smem[];
-  uint32_t* T = smem;
   const int W = blockDim.x >> 6;
-  uint32_t* red = smem + 1024;                                  // [W][RG][CG][4][64]
+  uint32_t* red = smem;                                         // [W][RG][CG][4][64]
   uint8_t* tr = (uint8_t*)(red + (size_t)W * RG * CG * 256);    // TRANS: [W][2][CG][16][64]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int jt = blockIdx.x % a.n_jt, kc = blockIdx.x / a.n_jt, mt = blockIdx.y;
@@ -508,15 +540,11 @@ __global__ void __launch_bounds__(1024) k_prod_stream(ProdArgs a, int ks_per_wav
 // ======================================================================================
 constexpr int STRIP_WAVES = 8;
 
-__device__ __forceinline__ v4i load_x(const int8_t* p, bool v) {
-  return v ? *(const v4i*)p : v4i{0, 0, 0, 0};
-}
-
-template <int CG, int RG>
+template <int CG, int RG, bool CMP>
 __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
+  __shared__ uint32_t T[1024];  // static: a compile-time address for the table lookups
   extern __shared__ uint32_t smem[];
-  uint32_t* T = smem;
-  uint8_t* strip = (uint8_t*)(smem + 1024);
+  uint8_t* strip = (uint8_t*)smem;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int total = a.n_jt * a.n_kc * a.n_mt;
   const int per = (total + 7) / 8;
@@ -530,6 +558,9 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
   const int k0 = kc * a.kc_len;
   const int k_len = min(a.kc_len, n - k0);
   const int ksteps = (k_len + 63) >> 6;
+  // The contraction loop runs three steps per iteration; the strip is padded with zero
+  // rows of A up to that multiple (a zero strip row adds nothing to any product).
+  const int kst = strip_steps(k_len);
   const uint32_t qmask = (1u << a.logq) - 1u;
   const uint32_t qmask2 = qmask * 0x10001u;
   const RoundKeys rk = load_rk(a.rkA);
@@ -538,19 +569,12 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
   __syncthreads();
 
   // ---- regenerate the strip ----
-  const int items = 16 * CG * ksteps * 8;
-  for (int t = threadIdx.x; t < items; t += blockDim.x) {
-    const int col_local = t / (ksteps * 8), kb = t % (ksteps * 8);
-    const int k = k0 + 8 * kb, col = nn0 + col_local;
-    uint32_t w[4] = {0, 0, 0, 0};
-    if (k < k0 + k_len) {
-      if (col < n) {
-        aes_ctr_block(T, rk, 0u, ((uint64_t)col * n + k) >> 3, w);
-      } else if (col < n + 8 && a.Bt) {
-        const uint4 bv = *(const uint4*)(a.Bt + 2 * ((size_t)(col - n) * n + k));
-        w[0] = bv.x; w[1] = bv.y; w[2] = bv.z; w[3] = bv.w;
-      }
-    }
+  // Four keystream blocks per thread and iteration, computed without branches (an entry
+  // outside A is overwritten afterwards) so that the AES chains interleave and hide the
+  // table-lookup latency.
+  const int items = 16 * CG * kst * 8;
+  auto put = [&](int t, const uint32_t (&w)[4]) {
+    const int col_local = t / (kst * 8), kb = t % (kst * 8);
     uint32_t lo0, hi0, lo1, hi1;
     limbs4(w[0] & qmask2, w[1] & qmask2, lo0, hi0);
     limbs4(w[2] & qmask2, w[3] & qmask2, lo1, hi1);
@@ -559,103 +583,209 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
     uint8_t* base = strip + ((size_t)((s * CG + cg) * 2) * 64 + lane_t) * 16 + h * 8;
     *(uint2*)base = make_uint2(lo0, lo1);
     *(uint2*)(base + 64 * 16) = make_uint2(hi0, hi1);
+  };
+  // entries outside A: zero padding rows, and the public-key columns (B^T) when present
+  auto fixup = [&](int t, uint32_t (&w)[4]) {
+    const int col_local = t / (kst * 8), kb = t % (kst * 8);
+    const int k = k0 + 8 * kb, col = nn0 + col_local;
+    if (k >= k0 + k_len || col >= n) {
+      w[0] = w[1] = w[2] = w[3] = 0;
+      if (k < k0 + k_len && col < n + 8 && a.Bt) {
+        const uint4 bv = *(const uint4*)(a.Bt + 2 * ((size_t)(col - n) * n + k));
+        w[0] = bv.x; w[1] = bv.y; w[2] = bv.z; w[3] = bv.w;
+      }
+    }
+  };
+  constexpr int ILP = 4;
+  for (int t0 = threadIdx.x; t0 < items; t0 += ILP * blockDim.x) {
+    int tt[ILP];
+    uint32_t w[ILP][4];
+#pragma unroll
+    for (int j = 0; j < ILP; ++j) {
+      const int t = t0 + j * blockDim.x;
+      tt[j] = t < items ? t : t0;  // past the end: recompute t0, stored once
+      const int c = nn0 + tt[j] / (kst * 8), k = k0 + 8 * (tt[j] % (kst * 8));
+      aes_ctr_block(T, rk, 0u, ((uint64_t)c * n + k) >> 3, w[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < ILP; ++j) {
+      fixup(tt[j], w[j]);
+      if (j == 0 || tt[j] != t0) put(tt[j], w[j]);
+    }
   }
   __syncthreads();
 
   // ---- stream the row tiles ----
+  // Each wave takes row blocks wave, wave + STRIP_WAVES, ...  Its loads form one continuous
+  // software pipeline over (row block, step): X fragments three steps deep (global loads
+  // issued two steps ahead, running into the next row block at the end of a block), strip
+  // fragments three deep (LDS reads one step ahead, wrapping to step 0).  The rings are
+  // indexed with compile-time slots in a three-step unrolled body (the strip is padded to a
+  // multiple of three steps), so no register moves tie a wait on a fresh load to the current
+  // step.  Rows past the chunk end read row m_begin instead (their results are never
+  // stored), and X loads past the last real step re-read it (they meet zero strip rows), so
+  // every operand load is unconditional and in bounds.
   const int m_begin = mt * a.m_tile, m_end = min(a.M, m_begin + a.m_tile);
   const int rows = m_end - m_begin;
   const int nrb = (rows + 16 * RG - 1) / (16 * RG);
-  for (int rb = wave; rb < nrb; rb += STRIP_WAVES) {
-    v4i acc[RG][CG][2];
-#pragma unroll
-    for (int rg = 0; rg < RG; ++rg)
-#pragma unroll
-      for (int cg = 0; cg < CG; ++cg) acc[rg][cg][0] = acc[rg][cg][1] = v4i{0, 0, 0, 0};
+  if (wave >= nrb) return;
+  const int klast = ksteps - 1;
+  // Fast tiles: the whole strip lies in B' (columns < n) and the contraction is not split,
+  // so the epilogue is E' add, mask and one 8-byte store (or compare) per tile.  The other
+  // workgroups (the strip holding V's columns, split-K) take the general epilogue.
+  const bool fast = a.n_kc == 1 && nn0 + 16 * CG <= n;
+  auto row_ptrs = [&](int rb, const int8_t* (&p)[RG]) {
     const int rbase = m_begin + rb * 16 * RG;
-    const int8_t* xp[RG];
-    bool xv[RG];
 #pragma unroll
     for (int rg = 0; rg < RG; ++rg) {
       const int row = rbase + rg * 16 + (lane & 15);
-      xv[rg] = row < m_end;
-      xp[rg] = a.X + (size_t)(xv[rg] ? row : m_begin) * a.ldx + k0 + 16 * (lane >> 4);
+      p[rg] = a.X + (size_t)(row < m_end ? row : m_begin) * a.ldx + k0 + 16 * (lane >> 4);
     }
-    // X fragments for steps s, s+1, s+2 in flight
-    v4i x0[RG], x1[RG], x2[RG];
+  };
+  const int8_t* xp[RG];  // current row block
+  const int8_t* xq[RG];  // next row block of this wave (the current one if there is none)
+  row_ptrs(wave, xp);
+  row_ptrs(wave + STRIP_WAVES < nrb ? wave + STRIP_WAVES : wave, xq);
+
+  v4i xb[3][RG];
+  v4i yb[3][CG][2];
+  auto load_xs = [&](v4i (&dst)[RG], const int8_t* const (&p)[RG], int s) {
 #pragma unroll
-    for (int rg = 0; rg < RG; ++rg) {
-      x0[rg] = load_x(xp[rg], xv[rg]);
-      x1[rg] = load_x(xp[rg] + 64, xv[rg] && ksteps > 1);
+    for (int rg = 0; rg < RG; ++rg) dst[rg] = *(const v4i*)(p[rg] + 64 * s);
+  };
+  auto load_ys = [&](v4i (&dst)[CG][2], int s) {
+#pragma unroll
+    for (int cg = 0; cg < CG; ++cg) {
+      dst[cg][0] = *(const v4i*)(strip + ((size_t)((s * CG + cg) * 2) * 64 + lane) * 16);
+      dst[cg][1] = *(const v4i*)(strip + ((size_t)((s * CG + cg) * 2 + 1) * 64 + lane) * 16);
     }
-    for (int s = 0; s < ksteps; ++s) {
+  };
+  v4i acc[RG][CG][2];
+  auto mma = [&](const v4i (&x)[RG], const v4i (&y)[CG][2]) {
 #pragma unroll
-      for (int rg = 0; rg < RG; ++rg) x2[rg] = load_x(xp[rg] + 64 * (s + 2), xv[rg] && s + 2 < ksteps);
-#pragma unroll
-      for (int cg = 0; cg < CG; ++cg) {
-        const v4i ylo = *(const v4i*)(strip + ((size_t)((s * CG + cg) * 2) * 64 + lane) * 16);
-        const v4i yhi = *(const v4i*)(strip + ((size_t)((s * CG + cg) * 2 + 1) * 64 + lane) * 16);
-#pragma unroll
-        for (int rg = 0; rg < RG; ++rg) {
-          acc[rg][cg][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ylo, x0[rg], acc[rg][cg][0], 0, 0, 0);
-          acc[rg][cg][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(yhi, x0[rg], acc[rg][cg][1], 0, 0, 0);
-        }
-      }
+    for (int cg = 0; cg < CG; ++cg)
 #pragma unroll
       for (int rg = 0; rg < RG; ++rg) {
-        x0[rg] = x1[rg];
-        x1[rg] = x2[rg];
+        acc[rg][cg][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(y[cg][0], x[rg], acc[rg][cg][0], 0, 0, 0);
+        acc[rg][cg][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(y[cg][1], x[rg], acc[rg][cg][1], 0, 0, 0);
       }
-    }
-    // epilogue: lane holds columns 4*(lane>>4) .. +3 of row (lane & 15) of each 16x16 tile
+  };
+  load_xs(xb[0], xp, 0);
+  load_xs(xb[1], xp, min(1, klast));
+  load_ys(yb[0], 0);
+  // The scheduling barriers keep each step's loads ahead of its MFMAs; the scheduler would
+  // otherwise sink them next to their first use and expose their latency.
+#define LWE_STRIP_STEP(U, XL, YL, T)                                       \
+  {                                                                        \
+    const int t2 = (T) + 2;                                                \
+    if (t2 < kst)                                                          \
+      load_xs(xb[XL], xp, min(t2, klast));                                 \
+    else                                                                   \
+      load_xs(xb[XL], xq, min(t2 - kst, klast));                           \
+    load_ys(yb[YL], (T) + 1 < kst ? (T) + 1 : 0);                          \
+    __builtin_amdgcn_sched_barrier(0);                                     \
+    mma(xb[U], yb[U]);                                                     \
+    __builtin_amdgcn_sched_barrier(0);                                     \
+  }
+
+  // One pass over this wave's row blocks; FAST selects the epilogue (uniform per workgroup).
+  auto run = [&](auto fast_tag) {
+    constexpr bool FAST = decltype(fast_tag)::value;
+    for (int rb = wave; rb < nrb; rb += STRIP_WAVES) {
+      const int rbase = m_begin + rb * 16 * RG;
 #pragma unroll
-    for (int rg = 0; rg < RG; ++rg) {
-      const int row = rbase + rg * 16 + (lane & 15);
-      const bool rvalid = row < m_end;
-      const int inst = row >> 3, r = row & 7;
-      uint32_t mism = 0;
+      for (int rg = 0; rg < RG; ++rg)
 #pragma unroll
-      for (int cg = 0; cg < CG; ++cg) {
-        const int col0 = nn0 + cg * 16 + 4 * (lane >> 4);
-        uint32_t D[4];
+        for (int cg = 0; cg < CG; ++cg) acc[rg][cg][0] = acc[rg][cg][1] = v4i{0, 0, 0, 0};
+      // Fast epilogue operands (E' words, and in compare mode the received ciphertext
+      // words), loaded now so that their latency hides behind the contraction.  The loads
+      // are unconditional (rows past the chunk end read row m_begin): no branch around them
+      // keeps the wait before their use exact.
+      uint32_t epre[RG][CG];
+      uint2 cpre[RG][CG];
+      if constexpr (FAST) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          D[i] = (uint32_t)acc[rg][cg][0][i] + ((uint32_t)acc[rg][cg][1][i] << 8);
-        if (!rvalid) continue;
-        if (a.n_kc > 1) {
+        for (int rg = 0; rg < RG; ++rg) {
+          const int row0 = rbase + rg * 16 + (lane & 15);
+          const int row = row0 < m_end ? row0 : m_begin;
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (col0 + i < a.ncols) atomicAdd((uint32_t*)&a.acc32[(size_t)row * a.acc_ld + col0 + i], D[i]);
-        } else if (col0 + 4 <= n) {
-          const uint32_t e4 = *(const uint32_t*)(a.E + (size_t)row * n + col0);
-          uint32_t v4[4];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) v4[i] = (D[i] + (uint32_t)(int32_t)(int8_t)(e4 >> (8 * i))) & qmask;
-          const uint2 packed = make_uint2(v4[0] | (v4[1] << 16), v4[2] | (v4[3] << 16));
-          const size_t off = a.out_off + 2 * ((size_t)r * n + col0);
-          if (a.mode == PM_COMPARE) {
-            const uint2 got = *(const uint2*)(a.cmp + (size_t)inst * a.cmp_stride + off);
-            mism |= (got.x ^ packed.x) | (got.y ^ packed.y);
-          } else {
-            *(uint2*)(a.out + (size_t)inst * a.out_stride + off) = packed;
+          for (int cg = 0; cg < CG; ++cg) {
+            const int col0 = nn0 + cg * 16 + 4 * (lane >> 4);
+            epre[rg][cg] = *(const uint32_t*)(a.E + (size_t)row * n + col0);
+            if constexpr (CMP)
+              cpre[rg][cg] = *(const uint2*)(a.cmp + (size_t)(row >> 3) * a.cmp_stride + a.out_off +
+                                             2 * ((size_t)(row & 7) * n + col0));
           }
-        } else {
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (col0 + i < a.ncols) mism |= epi_store(a, row, col0 + i, D[i]);
         }
       }
-      if (a.mode == PM_COMPARE && a.n_kc == 1) {
-        // rows 0-7 of the tile (lanes with (lane & 15) < 8) are one instance, rows 8-15 the next
-        const uint64_t bal = __ballot(mism != 0);
-        const int row_base = rbase + rg * 16;
-        if (lane == 0 && row_base < a.M)
-          atomicOr(&a.flags[row_base >> 3], (uint32_t)((bal & 0x00FF00FF00FF00FFull) != 0));
-        if (lane == 8 && row_base + 8 < a.M)
-          atomicOr(&a.flags[(row_base >> 3) + 1], (uint32_t)((bal & 0xFF00FF00FF00FF00ull) != 0));
+      for (int s = 0; s < kst; s += 3) {
+        LWE_STRIP_STEP(0, 2, 1, s);
+        LWE_STRIP_STEP(1, 0, 2, s + 1);
+        LWE_STRIP_STEP(2, 1, 0, s + 2);
+      }
+      // the next block's pointers become current; look one block further ahead
+#pragma unroll
+      for (int rg = 0; rg < RG; ++rg) xp[rg] = xq[rg];
+      {
+        const int nb = rb + 2 * STRIP_WAVES;
+        row_ptrs(nb < nrb ? nb : (rb + STRIP_WAVES < nrb ? rb + STRIP_WAVES : rb), xq);
+      }
+
+      // epilogue: lane holds columns 4*(lane>>4) .. +3 of row (lane & 15) of each 16x16 tile
+#pragma unroll
+      for (int rg = 0; rg < RG; ++rg) {
+        const int row = rbase + rg * 16 + (lane & 15);
+        const bool rvalid = row < m_end;
+        const int inst = row >> 3, r = row & 7;
+        uint32_t mism = 0;
+#pragma unroll
+        for (int cg = 0; cg < CG; ++cg) {
+          const int col0 = nn0 + cg * 16 + 4 * (lane >> 4);
+          uint32_t D[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            D[i] = (uint32_t)acc[rg][cg][0][i] + ((uint32_t)acc[rg][cg][1][i] << 8);
+          if constexpr (FAST) {
+            const uint32_t e4 = epre[rg][cg];
+            uint32_t v4[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v4[i] = (D[i] + (uint32_t)(int32_t)(int8_t)(e4 >> (8 * i))) & qmask;
+            const uint2 packed = make_uint2(v4[0] | (v4[1] << 16), v4[2] | (v4[3] << 16));
+            if constexpr (CMP) {
+              mism |= rvalid ? (cpre[rg][cg].x ^ packed.x) | (cpre[rg][cg].y ^ packed.y) : 0u;
+            } else if (rvalid) {
+              *(uint2*)(a.out + (size_t)inst * a.out_stride + a.out_off + 2 * ((size_t)r * n + col0)) = packed;
+            }
+          } else {
+            if (!rvalid) continue;
+            if (a.n_kc > 1) {
+#pragma unroll
+              for (int i = 0; i < 4; ++i)
+                if (col0 + i < a.ncols) atomicAdd((uint32_t*)&a.acc32[(size_t)row * a.acc_ld + col0 + i], D[i]);
+            } else {
+#pragma unroll
+              for (int i = 0; i < 4; ++i)
+                if (col0 + i < a.ncols) mism |= epi_store(a, row, col0 + i, D[i]);
+            }
+          }
+        }
+        if (CMP && a.n_kc == 1) {
+          // rows 0-7 of the tile (lanes with (lane & 15) < 8) are one instance, rows 8-15 the next
+          const uint64_t bal = __ballot(mism != 0);
+          const int row_base = rbase + rg * 16;
+          if (lane == 0 && row_base < a.M)
+            atomicOr(&a.flags[row_base >> 3], (uint32_t)((bal & 0x00FF00FF00FF00FFull) != 0));
+          if (lane == 8 && row_base + 8 < a.M)
+            atomicOr(&a.flags[(row_base >> 3) + 1], (uint32_t)((bal & 0xFF00FF00FF00FF00ull) != 0));
+        }
       }
     }
-  }
+  };
+  if (fast)
+    run(std::true_type{});
+  else
+    run(std::false_type{});
+#undef LWE_STRIP_STEP
 }
 
 // Completes split-K products: acc32 holds the full D for every (row, col).
@@ -1109,7 +1239,8 @@ hipError_t launch_sample(const SampleArgs& a, int count, hipStream_t s) {
 
 template <int CG, int RG, bool TRANS>
 static hipError_t launch_stream_t(const ProdArgs& a, int waves, int n_row_tiles, int ks, hipStream_t s) {
-  const size_t lds = 4096 + (size_t)waves * RG * CG * 256 * 4 + (TRANS ? (size_t)waves * 2 * CG * 1024 : 0);
+  // dynamic LDS only (the 4 KB of T-tables are static)
+  const size_t lds = (size_t)waves * RG * CG * 256 * 4 + (TRANS ? (size_t)waves * 2 * CG * 1024 : 0);
   hipLaunchKernelGGL((k_prod_stream<CG, RG, TRANS>), dim3((unsigned)(a.n_jt * a.n_kc), (unsigned)n_row_tiles),
                      dim3(64 * waves), lds, s, a, ks);
   return hipGetLastError();
@@ -1132,16 +1263,17 @@ hipError_t launch_product_stream(const ProdArgs& a, int cg, int rg, int waves, b
 }
 
 size_t product_strip_lds_bytes(int cg, int kc_len) {
-  const int ksteps = (kc_len + 63) / 64;
-  return 4096 + (size_t)ksteps * 64 * 16 * cg * 2;
+  return 4096 + (size_t)strip_steps(kc_len) * 64 * 16 * cg * 2;
 }
 
 template <int CG, int RG>
 static hipError_t launch_strip_t(const ProdArgs& a, hipStream_t s) {
-  const size_t lds = product_strip_lds_bytes(CG, a.kc_len);
+  // compare mode reads the received ciphertexts instead of writing them
+  auto kern = a.mode == PM_COMPARE ? k_prod_strip<CG, RG, true> : k_prod_strip<CG, RG, false>;
+  const size_t lds = product_strip_lds_bytes(CG, a.kc_len) - 4096;  // the T-tables are static
   const int total = a.n_jt * a.n_kc * a.n_mt;
   const unsigned grid = (unsigned)(8 * ((total + 7) / 8));
-  hipLaunchKernelGGL((k_prod_strip<CG, RG>), dim3(grid), dim3(64 * STRIP_WAVES), lds, s, a);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * STRIP_WAVES), lds, s, a);
   return hipGetLastError();
 }
 
@@ -1200,13 +1332,16 @@ hipError_t launch_final_ss(int count, const uint32_t* flags, const uint8_t* kpri
 
 template <int CG, int RG>
 static hipError_t allow_lds_strip() {
-  return hipFuncSetAttribute((const void*)k_prod_strip<CG, RG>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             160 * 1024);
+  hipError_t e = hipFuncSetAttribute((const void*)k_prod_strip<CG, RG, false>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 4096);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_prod_strip<CG, RG, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             160 * 1024 - 4096);
 }
 template <int CG, int RG, bool TR>
 static hipError_t allow_lds_stream() {
   return hipFuncSetAttribute((const void*)k_prod_stream<CG, RG, TR>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 4096);
 }
 
 hipError_t init_kernels() {

@@ -230,12 +230,17 @@ def _stream_ptr(args, stream) -> Optional[int]:
 class Context:
     """One lwe_ctx on one device (not thread-safe; use one per thread)."""
 
-    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, tuning: bool = True):
+        """tuning: apply the autotuner's table (tuning.json next to this file) if present."""
         self._lib = lib()
         h = C.c_void_p()
         _check(self._lib.lwe_ctx_create(C.byref(h), device, hbm_budget_bytes), "lwe_ctx_create")
         self._h = h
         self.device = device
+        if tuning:
+            from . import tune
+
+            tune.apply_table(self, tune.load_table())
 
     def close(self) -> None:
         if getattr(self, "_h", None):

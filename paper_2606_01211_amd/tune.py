@@ -1,0 +1,132 @@
+"""Autotuner of the batched product kernel's tile shape.
+
+For one lattice dimension and batch size it sweeps the strip width (16-column groups per
+workgroup), the rows per wave iteration and the number of row chunks sharing one
+regenerated strip of A, times the product kernel with the library's own HIP events, checks
+that every shape produces byte-identical ciphertexts (tile shapes must not change the
+arithmetic), and records the fastest shape in a JSON table:
+
+    {"<n>": {"col_groups": cg, "row_groups": rg, "m_chunks": mc, "us": t, "batch": b}, ...}
+
+Contexts created by the binding load the table next to this file (tuning.json) when it
+exists.
+
+    python -m paper_2606_01211_amd.tune --n 1344 --batch 4096
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TABLE = os.path.join(HERE, "tuning.json")
+
+# (col_groups, row_groups) pairs the library instantiates
+SHAPES = [(1, 1), (1, 2), (1, 4), (2, 1), (2, 2), (2, 4), (3, 1), (3, 2), (4, 1), (4, 2)]
+M_CHUNKS = [4, 6, 8, 12, 16, 24]
+
+
+def lds_fits(cg: int, n: int) -> bool:
+    """Whether a strip of 16*cg columns over the whole contraction fits LDS (the library
+    pads the strip to a multiple of three 64-row steps)."""
+    ksteps = ((n + 63) // 64 + 2) // 3 * 3
+    return 4096 + ksteps * 64 * 16 * cg * 2 <= 160 * 1024
+
+
+def load_table(path: str = TABLE) -> dict:
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def apply_table(ctx, table: dict) -> None:
+    from . import lwe
+
+    for n, t in table.items():
+        try:
+            pid = lwe.param_id(int(n))
+        except KeyError:
+            continue
+        ctx.set_tuning(pid, col_groups=t.get("col_groups", 0), row_groups=t.get("row_groups", 0),
+                       m_chunks=t.get("m_chunks", 0), host_hash_max=t.get("host_hash_max", 0))
+
+
+def tune(n: int, batch: int, reps: int = 3, verbose: bool = True) -> dict:
+    import torch
+
+    import lwe_inputs
+    from . import lwe
+
+    pid = lwe.param_id(n)
+    p = lwe.params(pid)
+    dev = torch.device("cuda:0")
+    ctx = lwe.Context(0)
+    g = lwe_inputs.rng(3, 77)
+    pk = np.concatenate([lwe_inputs.random_bytes(g, 1, 16)[0],
+                         (lwe_inputs.random_bytes(g, 1, 16 * n).view("<u2") & (2 ** p.logq - 1)).view(np.uint8)[0]])
+    d_pk = torch.from_numpy(pk.copy()).to(dev)
+    d_coins = torch.from_numpy(lwe_inputs.coins(g, batch)).to(dev)
+    d_mu = torch.from_numpy(lwe_inputs.messages(g, batch, p.mu_bytes)).to(dev)
+    d_ct = torch.empty((batch, p.ct_bytes), dtype=torch.uint8, device=dev)
+    results = []
+    ref_digest = None
+    for cg, rg in SHAPES:
+        if not lds_fits(cg, n):
+            continue
+        for mc in M_CHUNKS:
+            ctx.set_tuning(pid, col_groups=cg, row_groups=rg, m_chunks=mc)
+            ctx.test_encrypt(pid, batch, d_pk, d_coins, d_mu, d_ct)  # warm-up / buffer growth
+            torch.cuda.synchronize()
+            ctx.prof_reset()
+            ctx.prof_enable(True)
+            for _ in range(reps):
+                ctx.test_encrypt(pid, batch, d_pk, d_coins, d_mu, d_ct)
+            torch.cuda.synchronize()
+            prof = ctx.prof_read()
+            ctx.prof_enable(False)
+            launches, ms = prof.get("prod_strip", (0, 0.0))
+            if not launches:
+                continue
+            us = 1e3 * ms / launches
+            digest = hashlib.sha256(d_ct.cpu().numpy().tobytes()).hexdigest()
+            if ref_digest is None:
+                ref_digest = digest
+            same = digest == ref_digest
+            results.append({"col_groups": cg, "row_groups": rg, "m_chunks": mc, "us": us, "identical": same})
+            if verbose:
+                print("cg=%d rg=%d mc=%2d  %8.1f us  %s" % (cg, rg, mc, us, "ok" if same else "DIFFERENT"),
+                      flush=True)
+            if not same:
+                raise RuntimeError("tile shape cg=%d rg=%d mc=%d changed the ciphertexts" % (cg, rg, mc))
+    ctx.close()
+    best = min(results, key=lambda r: r["us"])
+    return {"col_groups": best["col_groups"], "row_groups": best["row_groups"], "m_chunks": best["m_chunks"],
+            "us": best["us"], "batch": batch, "sweep": results}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--n", type=int, nargs="+", default=[1344])
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--out", default=TABLE)
+    args = ap.parse_args(argv)
+    table = load_table(args.out)
+    for n in args.n:
+        best = tune(n, args.batch, args.reps)
+        sweep = best.pop("sweep")
+        table[str(n)] = best
+        print(json.dumps({"n": n, "best": best, "configs": len(sweep)}), flush=True)
+    with open(args.out, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
