@@ -350,7 +350,6 @@ int encrypt_core(lwe_ctx* c, int pid, const Params& p, size_t count, const uint8
   sa.X = X;
   sa.E = E;
   sa.E2 = E2;
-  sa.chunk = 2048;
   KLAUNCH("sample", s, launch_sample(sa, (int)count, s));
   ProdArgs a;
   memset(&a, 0, sizeof(a));
@@ -591,7 +590,6 @@ int lwe_keygen_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* seedA, co
   sa.X16 = osk.dev;  // S^T int16 at the start of each sk record
   sa.x16_stride = p.sk_bytes;
   sa.E = E;
-  sa.chunk = 2048;
   KLAUNCH("sample", s, launch_sample(sa, (int)count, s));
   ProdArgs a;
   memset(&a, 0, sizeof(a));

@@ -122,6 +122,70 @@ __device__ __forceinline__ RoundKeys load_rk(const uint32_t* __restrict__ rk) {
 }
 
 // ======================================================================================
+// AES with lane-replicated T-tables (conflict-free LDS lookups).  32 copies of T0 and of T2
+// (T2 = T0 rotated by 16): word e*64 + c holds T0[e] and word e*64 + 32 + c holds T2[e], for
+// copy c = lane & 31, so the 32 lanes of a half-wave always read 32 different banks.  The
+// byte address of a lookup, state byte * 256 + copy offset, is one v_perm_b32.  T1 and T3
+// are T0 and T2 rotated by 8, so each column XORs its T1 and T3 terms first and rotates once:
+//   t_j = T0[s_j.b0] ^ T2[s_j+2.b2] ^ rotl8(T0[s_j+1.b1] ^ T2[s_j+3.b3] ^ rotr8(rk)).
+// 64 KB of LDS.
+// ======================================================================================
+constexpr int TR_WORDS = 256 * 64;
+
+__device__ __forceinline__ void load_tables_rep(uint32_t* TR, const uint32_t* __restrict__ T0) {
+  for (int i = threadIdx.x; i < TR_WORDS; i += blockDim.x) {
+    const uint32_t v = T0[i >> 6];
+    TR[i] = (i & 32) ? rotl32(v, 16) : v;
+  }
+}
+
+// Entry of the replicated table for byte BYTE of x; `off` = copy offset (+128 for T2).
+template <int BYTE>
+__device__ __forceinline__ uint32_t rep_look(const uint32_t* __restrict__ TR, uint32_t x, uint32_t off) {
+  // byte 1 of the address <- byte BYTE of x, byte 0 <- byte 0 of off, bytes 2, 3 <- 0
+  const uint32_t addr = __builtin_amdgcn_perm(x, off, 0x0c0c0000u | ((4u + BYTE) << 8));
+  return *(const uint32_t*)((const char*)TR + addr);
+}
+
+// One CTR keystream block (same definition as aes_ctr_block).  rkr[r] = rotr8 of round key
+// word 4 + r (rounds 1-9), so that the round key folds into the rotated half.
+template <class RK>
+__device__ __forceinline__ void aes_ctr_block_rep(const uint32_t* __restrict__ TR, uint32_t off0,
+                                                  uint32_t off2, const RK& rk, const uint32_t* rkr,
+                                                  uint32_t dom_le, uint64_t b, uint32_t o[4]) {
+  uint32_t s[4];
+  s[0] = dom_le ^ rk[0];
+  s[1] = rk[1];
+  s[2] = bswap32((uint32_t)(b >> 32)) ^ rk[2];
+  s[3] = bswap32((uint32_t)b) ^ rk[3];
+#pragma unroll
+  for (int r = 1; r < 10; ++r) {
+    uint32_t t[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t a0 = rep_look<0>(TR, s[j], off0);
+      const uint32_t a1 = rep_look<1>(TR, s[(j + 1) & 3], off0);
+      const uint32_t a2 = rep_look<2>(TR, s[(j + 2) & 3], off2);
+      const uint32_t a3 = rep_look<3>(TR, s[(j + 3) & 3], off2);
+      t[j] = x3(a0, a2, rotl32(x3(a1, a3, rkr[4 * (r - 1) + j]), 8));
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s[j] = t[j];
+  }
+  // Final round: S(x) is byte 2 of T0[x].
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t a0 = rep_look<0>(TR, s[j], off0);
+    const uint32_t a1 = rep_look<1>(TR, s[(j + 1) & 3], off0);
+    const uint32_t a2 = rep_look<2>(TR, s[(j + 2) & 3], off0);
+    const uint32_t a3 = rep_look<3>(TR, s[(j + 3) & 3], off0);
+    const uint32_t lo = __builtin_amdgcn_perm(a1, a0, 0x0c0c0602u);  // S(a0), S(a1) in bytes 0, 1
+    const uint32_t hi = __builtin_amdgcn_perm(a3, a2, 0x06020c0cu);  // S(a2), S(a3) in bytes 2, 3
+    o[j] = x3(lo, hi, rk[40 + j]);
+  }
+}
+
+// ======================================================================================
 // Limb split: a 16-bit value x (already reduced mod q) equals lo + 256 hi (mod 2^16) with
 // lo = sext8(x & 0xff) and hi = sext8(((x + 0x80) >> 8) & 0xff).  The int8 byte of lo is the
 // low byte of x itself.
@@ -257,52 +321,74 @@ __global__ void k_sample_stream(SampTable st, int K, const uint32_t* __restrict_
 // instance.  Keystream domains: 1 -> segment 0, 2 -> segment 1, 3 -> segment 2.  Every AES
 // block gives 8 consecutive samples of one matrix row.
 // ======================================================================================
+// compute units of the current device (set by init_kernels; sizes persistent grids)
+static int g_num_cus = 256;
+
+constexpr int SAMPLE_ILP = 4;   // AES blocks per lane per unit
+constexpr int SAMPLE_WAVES = 8; // waves per workgroup
+
 template <int KT>
-__global__ void __launch_bounds__(256) k_sample(SampleArgs a) {
-  __shared__ uint32_t T[1024];
-  const int inst = blockIdx.y;
-  const RoundKeys rk = load_rk(a.rk + (size_t)inst * 44);
-  load_tables(T, a.T0);
-  const int n = a.n;
-  if (blockIdx.x == 0 && a.ldx > n) {  // zero the padding columns of segment 0
-    const int pad = a.ldx - n;
-    for (int idx = threadIdx.x; idx < 8 * pad; idx += blockDim.x)
-      a.X[((size_t)inst * 8 + idx / pad) * a.ldx + n + idx % pad] = 0;
-  }
+__global__ void __launch_bounds__(64 * SAMPLE_WAVES) k_sample(SampleArgs a, int count) {
+  __shared__ uint32_t TR[TR_WORDS];
+  load_tables_rep(TR, a.T0);
   __syncthreads();
-  const int total = 2 * n + (a.nseg == 3 ? 8 : 0);
-  const int t_end = min(total, (int)(blockIdx.x + 1) * a.chunk);
-  for (int t = blockIdx.x * a.chunk + threadIdx.x; t < t_end; t += blockDim.x) {
-    int seg, lb;
-    if (t < n) {
-      seg = 0;
-      lb = t;
-    } else if (t < 2 * n) {
-      seg = 1;
-      lb = t - n;
-    } else {
-      seg = 2;
-      lb = t - 2 * n;
-    }
-    uint32_t o[4];
-    aes_ctr_block(T, rk, bswap32((uint32_t)(seg + 1)), (uint64_t)lb, o);
-    uint32_t h[4];  // samples 2k, 2k+1 as int16 halves
+  const int lane = threadIdx.x & 63;
+  const uint32_t off0 = (uint32_t)(lane & 31) << 2, off2 = off0 + 128;
+  const int n = a.n;
+  const int total = 2 * n + (a.nseg == 3 ? 8 : 0);  // AES blocks per instance
+  // Work unit = 64 * SAMPLE_ILP consecutive blocks of one instance, taken by one wave, so
+  // that the instance's round keys are wave-uniform (scalar registers).
+  const int per_unit = 64 * SAMPLE_ILP;
+  const int units_per_inst = (total + per_unit - 1) / per_unit;
+  const int n_units = units_per_inst * count;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int nwaves = gridDim.x * SAMPLE_WAVES;
+  for (int u = blockIdx.x * SAMPLE_WAVES + wave; u < n_units; u += nwaves) {
+    const int inst = u / units_per_inst, chunk = u - inst * units_per_inst;
+    const RoundKeys rk = load_rk(a.rk + (size_t)inst * 44);
+    uint32_t rkr[36];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) h[q] = sample_pair<KT>(o[q], a.T2, a.K);
-    const uint32_t p0 = __builtin_amdgcn_perm(h[1], h[0], 0x06040200u);  // low bytes = int8 samples
-    const uint32_t p1 = __builtin_amdgcn_perm(h[3], h[2], 0x06040200u);
-    const int w0 = 8 * lb;
-    if (seg == 0) {
-      const int row = w0 / n, col = w0 % n;
-      *(uint2*)(a.X + ((size_t)inst * 8 + row) * a.ldx + col) = make_uint2(p0, p1);
-      if (a.X16)
-        *(uint4*)(a.X16 + (size_t)inst * a.x16_stride + 2 * ((size_t)row * n + col)) =
-            make_uint4(h[0], h[1], h[2], h[3]);
-    } else if (seg == 1) {
-      const int row = w0 / n, col = w0 % n;
-      *(uint2*)(a.E + ((size_t)inst * 8 + row) * n + col) = make_uint2(p0, p1);
-    } else {
-      *(uint2*)(a.E2 + (size_t)inst * 64 + w0) = make_uint2(p0, p1);
+    for (int i = 0; i < 36; ++i) rkr[i] = rotl32(rk[4 + i], 24);
+    if (chunk == 0 && a.ldx > n) {  // zero the padding columns of segment 0
+      const int pad = a.ldx - n;
+      for (int idx = lane; idx < 8 * pad; idx += 64)
+        a.X[((size_t)inst * 8 + idx / pad) * a.ldx + n + idx % pad] = 0;
+    }
+    uint32_t o[SAMPLE_ILP][4];
+    int tt[SAMPLE_ILP];
+#pragma unroll
+    for (int j = 0; j < SAMPLE_ILP; ++j) {
+      const int t = chunk * per_unit + j * 64 + lane;
+      tt[j] = t;
+      const int tc = t < total ? t : total - 1;
+      const int seg = tc < n ? 0 : (tc < 2 * n ? 1 : 2);
+      const int lb = tc - seg * n;
+      aes_ctr_block_rep(TR, off0, off2, rk, rkr, bswap32((uint32_t)(seg + 1)), (uint64_t)lb, o[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < SAMPLE_ILP; ++j) {
+      const int t = tt[j];
+      if (t >= total) continue;
+      const int seg = t < n ? 0 : (t < 2 * n ? 1 : 2);
+      const int lb = t - seg * n;
+      uint32_t h[4];  // samples 2k, 2k+1 as int16 halves
+#pragma unroll
+      for (int q = 0; q < 4; ++q) h[q] = sample_pair<KT>(o[j][q], a.T2, a.K);
+      const uint32_t p0 = __builtin_amdgcn_perm(h[1], h[0], 0x06040200u);  // low bytes = int8 samples
+      const uint32_t p1 = __builtin_amdgcn_perm(h[3], h[2], 0x06040200u);
+      const int w0 = 8 * lb;
+      if (seg == 0) {
+        const int row = w0 / n, col = w0 - row * n;
+        *(uint2*)(a.X + ((size_t)inst * 8 + row) * a.ldx + col) = make_uint2(p0, p1);
+        if (a.X16)
+          *(uint4*)(a.X16 + (size_t)inst * a.x16_stride + 2 * ((size_t)row * n + col)) =
+              make_uint4(h[0], h[1], h[2], h[3]);
+      } else if (seg == 1) {
+        const int row = w0 / n, col = w0 - row * n;
+        *(uint2*)(a.E + ((size_t)inst * 8 + row) * n + col) = make_uint2(p0, p1);
+      } else {
+        *(uint2*)(a.E2 + (size_t)inst * 64 + w0) = make_uint2(p0, p1);
+      }
     }
   }
 }
@@ -569,25 +655,33 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
   __syncthreads();
 
   // ---- regenerate the strip ----
-  // Four keystream blocks per thread and iteration, computed without branches (an entry
-  // outside A is overwritten afterwards) so that the AES chains interleave and hide the
-  // table-lookup latency.
+  // Item t = one AES block = 8 consecutive contraction rows of one column.  Items are
+  // numbered so that consecutive lanes fill consecutive 16-byte fragment slots (conflict-free
+  // LDS stores): t = (((s * CG + cg) * 4 + g) * 2 + h) * 16 + c16, where the block covers rows
+  // s*64 + g*16 + h*8 .. +7 of column 16*cg + c16 and lands in fragment lane g*16 + c16,
+  // bytes h*8 .. +7.  Four blocks per thread and iteration, computed without branches (an
+  // entry outside A is overwritten afterwards), so that the AES chains interleave.
   const int items = 16 * CG * kst * 8;
+  struct Item {
+    int col_local, kb;
+  };
+  auto item = [&](int t) {
+    const int c16 = t & 15, h = (t >> 4) & 1, g = (t >> 5) & 3, rest = t >> 7;
+    return Item{(rest % CG) * 16 + c16, (rest / CG) * 8 + g * 2 + h};
+  };
   auto put = [&](int t, const uint32_t (&w)[4]) {
-    const int col_local = t / (kst * 8), kb = t % (kst * 8);
     uint32_t lo0, hi0, lo1, hi1;
     limbs4(w[0] & qmask2, w[1] & qmask2, lo0, hi0);
     limbs4(w[2] & qmask2, w[3] & qmask2, lo1, hi1);
-    const int s = kb >> 3, g = (kb & 7) >> 1, h = kb & 1;
-    const int lane_t = g * 16 + (col_local & 15), cg = col_local >> 4;
-    uint8_t* base = strip + ((size_t)((s * CG + cg) * 2) * 64 + lane_t) * 16 + h * 8;
+    // fragment (s, cg, limb) base + lane slot: the same numbering as t without its h bit
+    const int c16 = t & 15, h = (t >> 4) & 1, g = (t >> 5) & 3, rest = t >> 7;
+    uint8_t* base = strip + ((size_t)(rest * 2) * 64 + g * 16 + c16) * 16 + h * 8;
     *(uint2*)base = make_uint2(lo0, lo1);
     *(uint2*)(base + 64 * 16) = make_uint2(hi0, hi1);
   };
   // entries outside A: zero padding rows, and the public-key columns (B^T) when present
-  auto fixup = [&](int t, uint32_t (&w)[4]) {
-    const int col_local = t / (kst * 8), kb = t % (kst * 8);
-    const int k = k0 + 8 * kb, col = nn0 + col_local;
+  auto fixup = [&](const Item& it, uint32_t (&w)[4]) {
+    const int k = k0 + 8 * it.kb, col = nn0 + it.col_local;
     if (k >= k0 + k_len || col >= n) {
       w[0] = w[1] = w[2] = w[3] = 0;
       if (k < k0 + k_len && col < n + 8 && a.Bt) {
@@ -604,12 +698,13 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
     for (int j = 0; j < ILP; ++j) {
       const int t = t0 + j * blockDim.x;
       tt[j] = t < items ? t : t0;  // past the end: recompute t0, stored once
-      const int c = nn0 + tt[j] / (kst * 8), k = k0 + 8 * (tt[j] % (kst * 8));
+      const Item it = item(tt[j]);
+      const int c = nn0 + it.col_local, k = k0 + 8 * it.kb;
       aes_ctr_block(T, rk, 0u, ((uint64_t)c * n + k) >> 3, w[j]);
     }
 #pragma unroll
     for (int j = 0; j < ILP; ++j) {
-      fixup(tt[j], w[j]);
+      fixup(item(tt[j]), w[j]);
       if (j == 0 || tt[j] != t0) put(tt[j], w[j]);
     }
   }
@@ -647,46 +742,50 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
   row_ptrs(wave, xp);
   row_ptrs(wave + STRIP_WAVES < nrb ? wave + STRIP_WAVES : wave, xq);
 
-  v4i xb[3][RG];
-  v4i yb[3][CG][2];
+  v4i xb[3][RG];  // X ring: slot = step mod 3
+  v4i yb[3][2];   // strip fragment ring: slot = phase mod 3, a phase being one (step, cg)
   auto load_xs = [&](v4i (&dst)[RG], const int8_t* const (&p)[RG], int s) {
 #pragma unroll
     for (int rg = 0; rg < RG; ++rg) dst[rg] = *(const v4i*)(p[rg] + 64 * s);
   };
-  auto load_ys = [&](v4i (&dst)[CG][2], int s) {
-#pragma unroll
-    for (int cg = 0; cg < CG; ++cg) {
-      dst[cg][0] = *(const v4i*)(strip + ((size_t)((s * CG + cg) * 2) * 64 + lane) * 16);
-      dst[cg][1] = *(const v4i*)(strip + ((size_t)((s * CG + cg) * 2 + 1) * 64 + lane) * 16);
-    }
+  auto load_y = [&](v4i (&dst)[2], int s, int cg) {
+    dst[0] = *(const v4i*)(strip + ((size_t)((s * CG + cg) * 2) * 64 + lane) * 16);
+    dst[1] = *(const v4i*)(strip + ((size_t)((s * CG + cg) * 2 + 1) * 64 + lane) * 16);
   };
   v4i acc[RG][CG][2];
-  auto mma = [&](const v4i (&x)[RG], const v4i (&y)[CG][2]) {
-#pragma unroll
-    for (int cg = 0; cg < CG; ++cg)
-#pragma unroll
-      for (int rg = 0; rg < RG; ++rg) {
-        acc[rg][cg][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(y[cg][0], x[rg], acc[rg][cg][0], 0, 0, 0);
-        acc[rg][cg][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(y[cg][1], x[rg], acc[rg][cg][1], 0, 0, 0);
-      }
-  };
   load_xs(xb[0], xp, 0);
   load_xs(xb[1], xp, min(1, klast));
-  load_ys(yb[0], 0);
-  // The scheduling barriers keep each step's loads ahead of its MFMAs; the scheduler would
-  // otherwise sink them next to their first use and expose their latency.
-#define LWE_STRIP_STEP(U, XL, YL, T)                                       \
-  {                                                                        \
-    const int t2 = (T) + 2;                                                \
-    if (t2 < kst)                                                          \
-      load_xs(xb[XL], xp, min(t2, klast));                                 \
-    else                                                                   \
-      load_xs(xb[XL], xq, min(t2 - kst, klast));                           \
-    load_ys(yb[YL], (T) + 1 < kst ? (T) + 1 : 0);                          \
-    __builtin_amdgcn_sched_barrier(0);                                     \
-    mma(xb[U], yb[U]);                                                     \
-    __builtin_amdgcn_sched_barrier(0);                                     \
-  }
+  load_y(yb[0], 0, 0);
+  // Three steps per iteration (the strip is padded to a multiple of three).  At each step the
+  // X fragments of step + 2 are requested; at each phase the strip fragments of the next
+  // phase (wrapping from the last step to step 0, the strip being the same for every row
+  // block).  Scheduling barriers keep every request ahead of the MFMAs that hide it; the
+  // scheduler would otherwise sink the loads next to their first use.
+  auto three_steps = [&](int s) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int t = s + i, t2 = t + 2;
+      if (t2 < kst)
+        load_xs(xb[(i + 2) % 3], xp, min(t2, klast));
+      else
+        load_xs(xb[(i + 2) % 3], xq, min(t2 - kst, klast));
+#pragma unroll
+      for (int cg = 0; cg < CG; ++cg) {
+        const int ph = i * CG + cg;
+        if (cg + 1 < CG)
+          load_y(yb[(ph + 1) % 3], t, cg + 1);
+        else
+          load_y(yb[(ph + 1) % 3], t + 1 < kst ? t + 1 : 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int rg = 0; rg < RG; ++rg) {
+          acc[rg][cg][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(yb[ph % 3][0], xb[i][rg], acc[rg][cg][0], 0, 0, 0);
+          acc[rg][cg][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(yb[ph % 3][1], xb[i][rg], acc[rg][cg][1], 0, 0, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  };
 
   // One pass over this wave's row blocks; FAST selects the epilogue (uniform per workgroup).
   auto run = [&](auto fast_tag) {
@@ -718,11 +817,7 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
           }
         }
       }
-      for (int s = 0; s < kst; s += 3) {
-        LWE_STRIP_STEP(0, 2, 1, s);
-        LWE_STRIP_STEP(1, 0, 2, s + 1);
-        LWE_STRIP_STEP(2, 1, 0, s + 2);
-      }
+      for (int s = 0; s < kst; s += 3) three_steps(s);
       // the next block's pointers become current; look one block further ahead
 #pragma unroll
       for (int rg = 0; rg < RG; ++rg) xp[rg] = xq[rg];
@@ -762,10 +857,47 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
 #pragma unroll
               for (int i = 0; i < 4; ++i)
                 if (col0 + i < a.ncols) atomicAdd((uint32_t*)&a.acc32[(size_t)row * a.acc_ld + col0 + i], D[i]);
-            } else {
+            } else if (col0 + 4 <= n) {
+              // a B' (or B^T) tile of the edge strip: as in the fast path
+              const uint32_t e4 = *(const uint32_t*)(a.E + (size_t)row * n + col0);
+              uint32_t v4[4];
+#pragma unroll
+              for (int i = 0; i < 4; ++i) v4[i] = (D[i] + (uint32_t)(int32_t)(int8_t)(e4 >> (8 * i))) & qmask;
+              const uint2 packed = make_uint2(v4[0] | (v4[1] << 16), v4[2] | (v4[3] << 16));
+              const size_t off = a.out_off + 2 * ((size_t)r * n + col0);
+              if constexpr (CMP) {
+                const uint2 got = *(const uint2*)(a.cmp + (size_t)inst * a.cmp_stride + off);
+                mism |= (got.x ^ packed.x) | (got.y ^ packed.y);
+              } else {
+                *(uint2*)(a.out + (size_t)inst * a.out_stride + off) = packed;
+              }
+            } else if (col0 + 4 <= a.ncols) {
+              // Four V coefficients c0 .. c0+3 of row r: V = D + E'' + enc(mu).  (n is a
+              // multiple of 8, so a tile never straddles column n; columns past ncols are
+              // padding.)
+              const int c0 = col0 - n, coeff = r * 8 + c0;
+              const uint32_t e4 = *(const uint32_t*)(a.E2 + (size_t)inst * 64 + coeff);
+              const uint8_t* mu = a.mu + (size_t)inst * a.mu_stride;
+              const int mb = 8 * a.B, bit = coeff * a.B, byte = bit >> 3, sh = bit & 7;
+              uint32_t win = 0;  // message bits from bit `bit` on (at most 4B + 7 <= 31 bits used)
+#pragma unroll
+              for (int kb = 0; kb < 4; ++kb)
+                if (byte + kb < mb) win |= (uint32_t)mu[byte + kb] << (8 * kb);
+              win >>= sh;
+              const uint32_t kmask = (1u << a.B) - 1u;
+              uint32_t v4[4];
 #pragma unroll
               for (int i = 0; i < 4; ++i)
-                if (col0 + i < a.ncols) mism |= epi_store(a, row, col0 + i, D[i]);
+                v4[i] = (D[i] + (uint32_t)(int32_t)(int8_t)(e4 >> (8 * i)) +
+                         (((win >> (i * a.B)) & kmask) << (a.logq - a.B))) & qmask;
+              const uint2 packed = make_uint2(v4[0] | (v4[1] << 16), v4[2] | (v4[3] << 16));
+              const size_t off = 2 * ((size_t)8 * n + coeff);
+              if constexpr (CMP) {
+                const uint2 got = *(const uint2*)(a.cmp + (size_t)inst * a.cmp_stride + off);
+                mism |= (got.x ^ packed.x) | (got.y ^ packed.y);
+              } else {
+                *(uint2*)(a.out + (size_t)inst * a.out_stride + off) = packed;
+              }
             }
           }
         }
@@ -785,7 +917,6 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
     run(std::true_type{});
   else
     run(std::false_type{});
-#undef LWE_STRIP_STEP
 }
 
 // Completes split-K products: acc32 holds the full D for every (row, col).
@@ -1010,7 +1141,9 @@ __device__ __forceinline__ uint32_t keccak_rc_half(int round, int parity) {
 
 __device__ __forceinline__ void keccak_f1600_pair(uint32_t s[25], uint32_t p) {
   const uint32_t sh1 = p ? 0u : 31u;  // rotation of the partner's C[x+1] by 1 (even half) or 0
-#pragma unroll 1
+  // Fully unrolled: pi then costs no register moves (its position cycle has length 24) and
+  // the round constants become immediates.
+#pragma unroll
   for (int round = 0; round < 24; ++round) {
     uint32_t c[5];
 #pragma unroll
@@ -1085,54 +1218,53 @@ __global__ void __launch_bounds__(64) k_hash_records(int count, const uint8_t* _
   uint32_t s[25];
 #pragma unroll
   for (int k = 0; k < 25; ++k) s[k] = 0;
-  const size_t nfull = len / SHA3_RATE;
+  const size_t nfull = len / SHA3_RATE;  // full rate blocks; block nfull is the padded last one
   const bool aligned = (((uintptr_t)base) & 3) == 0;
-  size_t off = 0;
-  if (aligned && nfull > 0) {
-    const uint32_t* q = (const uint32_t*)base + p;
-    uint32_t cur[17], nxt[17];
+  // Raw message words of block b for this lane (bytes 8w + 4p .. 8w + 4p + 3 of the block).
+  // The last block carries the remaining bytes, the domain bits 01 and pad10*1.  No lane
+  // exchange happens in here (the branches may diverge between records).
+  auto load_block = [&](size_t b, uint32_t (&m)[17]) {
+    const size_t off = b * SHA3_RATE;
+    if (b < nfull && aligned) {
+      const uint32_t* q = (const uint32_t*)(base + off) + p;
 #pragma unroll
-    for (int w = 0; w < 17; ++w) cur[w] = q[2 * w];
-    for (size_t b = 0; b < nfull; ++b) {
-      const bool more = b + 1 < nfull;
-      const uint32_t* qn = q + (b + 1) * (SHA3_RATE / 4);
-#pragma unroll
-      for (int w = 0; w < 17; ++w) nxt[w] = more ? qn[2 * w] : 0u;
-#pragma unroll
-      for (int w = 0; w < 17; ++w) s[w] ^= interleave_in(cur[w], p);
-      keccak_f1600_pair(s, p);
-#pragma unroll
-      for (int w = 0; w < 17; ++w) cur[w] = nxt[w];
-    }
-    off = nfull * SHA3_RATE;
-  } else {
-    for (size_t b = 0; b < nfull; ++b, off += SHA3_RATE) {
+      for (int w = 0; w < 17; ++w) m[w] = q[2 * w];
+    } else {
+      const bool last = b == nfull;
+      const int rem = last ? (int)(len - off) : SHA3_RATE;
 #pragma unroll
       for (int w = 0; w < 17; ++w) {
         uint32_t v = 0;
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb) v |= (uint32_t)base[off + 8 * w + 4 * p + kb] << (8 * kb);
-        s[w] ^= interleave_in(v, p);
+        for (int kb = 0; kb < 4; ++kb) {
+          const int pos = 8 * w + 4 * (int)p + kb;
+          uint32_t byte = pos < rem ? (uint32_t)base[off + pos] : 0u;
+          if (last && pos == rem) byte ^= 0x06u;
+          if (last && pos == SHA3_RATE - 1) byte ^= 0x80u;
+          v |= byte << (8 * kb);
+        }
+        m[w] = v;
       }
-      keccak_f1600_pair(s, p);
     }
-  }
-  // final block: remaining bytes, the domain bits 01 and pad10*1
-  const int rem = (int)(len - off);
+  };
+  // One absorption loop (one inlined copy of the permutation); the next block is fetched
+  // while the current one is permuted.
+  uint32_t cur[17];
+  load_block(0, cur);
+  for (size_t b = 0; b <= nfull; ++b) {
+    uint32_t nxt[17];
+    if (b < nfull) {
+      load_block(b + 1, nxt);
+    } else {
 #pragma unroll
-  for (int w = 0; w < 17; ++w) {
-    uint32_t v = 0;
-#pragma unroll
-    for (int kb = 0; kb < 4; ++kb) {
-      const int pos = 8 * w + 4 * (int)p + kb;
-      uint32_t byte = pos < rem ? (uint32_t)base[off + pos] : 0u;
-      if (pos == rem) byte ^= 0x06u;
-      if (pos == SHA3_RATE - 1) byte ^= 0x80u;
-      v |= byte << (8 * kb);
+      for (int w = 0; w < 17; ++w) nxt[w] = 0;
     }
-    s[w] ^= interleave_in(v, p);
+#pragma unroll
+    for (int w = 0; w < 17; ++w) s[w] ^= interleave_in(cur[w], p);
+    keccak_f1600_pair(s, p);
+#pragma unroll
+    for (int w = 0; w < 17; ++w) cur[w] = nxt[w];
   }
-  keccak_f1600_pair(s, p);
   // digest: words 0..3 re-interleaved by the even lane
   uint32_t d[8];
 #pragma unroll
@@ -1225,14 +1357,15 @@ hipError_t launch_sample_stream(const Params& p, const uint32_t* rk, const uint3
 
 hipError_t launch_sample(const SampleArgs& a, int count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
+  // persistent waves: at most two workgroups (64 KB of tables each) per CU
   const int total = 2 * a.n + (a.nseg == 3 ? 8 : 0);
-  const unsigned gx = (unsigned)((total + a.chunk - 1) / a.chunk);
-  const dim3 grid(gx, (unsigned)count);
+  const long long units = (long long)((total + 64 * SAMPLE_ILP - 1) / (64 * SAMPLE_ILP)) * count;
+  const unsigned grid = (unsigned)std::min<long long>((units + SAMPLE_WAVES - 1) / SAMPLE_WAVES, 2 * g_num_cus);
   switch (a.K) {
-    case 6: hipLaunchKernelGGL(k_sample<6>, grid, dim3(256), 0, s, a); break;
-    case 10: hipLaunchKernelGGL(k_sample<10>, grid, dim3(256), 0, s, a); break;
-    case 12: hipLaunchKernelGGL(k_sample<12>, grid, dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL(k_sample<0>, grid, dim3(256), 0, s, a); break;
+    case 6: hipLaunchKernelGGL(k_sample<6>, dim3(grid), dim3(64 * SAMPLE_WAVES), 0, s, a, count); break;
+    case 10: hipLaunchKernelGGL(k_sample<10>, dim3(grid), dim3(64 * SAMPLE_WAVES), 0, s, a, count); break;
+    case 12: hipLaunchKernelGGL(k_sample<12>, dim3(grid), dim3(64 * SAMPLE_WAVES), 0, s, a, count); break;
+    default: hipLaunchKernelGGL(k_sample<0>, dim3(grid), dim3(64 * SAMPLE_WAVES), 0, s, a, count); break;
   }
   return hipGetLastError();
 }
@@ -1346,6 +1479,12 @@ static hipError_t allow_lds_stream() {
 
 hipError_t init_kernels() {
   hipError_t e = hipSuccess, r;
+  {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+      g_num_cus = cus;
+  }
 #define LWE_TRY(x) \
   if ((r = (x)) != hipSuccess) e = r;
   LWE_TRY((allow_lds_strip<1, 1>()))

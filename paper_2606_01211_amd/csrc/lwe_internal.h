@@ -63,7 +63,6 @@ struct SampleArgs {
   size_t x16_stride;
   int8_t* E;             // segment 1 (domain 2): [count*8][n]
   int8_t* E2;            // segment 2 (domain 3): [count][64]
-  int chunk;             // AES blocks per workgroup
 };
 
 struct DecArgs {
