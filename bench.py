@@ -21,6 +21,7 @@ import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -53,7 +54,7 @@ def parse():
     ap.add_argument("--n", type=int, default=1344)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--plain", type=int, default=300, help="plain encaps and decaps calls timed one by one")
-    ap.add_argument("--streams", type=int, default=2,
+    ap.add_argument("--streams", type=int, default=4,
                     help="independent steps in flight (one library context and HIP stream each); the "
                          "serial rate (one stream) is always measured too")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="budget of the CPU oracle leg")
@@ -129,23 +130,41 @@ def main():
     print("warmup done", file=sys.stderr, flush=True)
 
     def timed(lanes, first_seed):
-        """K steps spread round-robin over `lanes` streams; returns wall seconds, per-step
-        device latencies (ms) and the merged kernel profile."""
+        """K steps spread round-robin over `lanes` streams, each stream fed by its own host
+        thread (a library call that hashes on the host waits for its own stream only; the
+        calls release the interpreter lock).  Returns wall seconds, per-step device
+        latencies (ms) and the merged kernel profile."""
         for c in ctxs:
             c.prof_reset()
             c.prof_enable(True)
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+        errors = []
+
+        def feed(lane):
+            try:
+                for i in range(lane, K, lanes):
+                    with torch.cuda.stream(streams[lane]):
+                        ev[i][0].record()
+                    step(first_seed + i, lane)
+                    with torch.cuda.stream(streams[lane]):
+                        ev[i][1].record()
+            except Exception as e:  # surfaced after the join
+                errors.append(e)
+
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for i in range(K):
-            lane = i % lanes
-            with torch.cuda.stream(streams[lane]):
-                ev[i][0].record()
-            step(first_seed + i, lane)
-            with torch.cuda.stream(streams[lane]):
-                ev[i][1].record()
+        if lanes == 1:
+            feed(0)
+        else:
+            th = [threading.Thread(target=feed, args=(lane,)) for lane in range(lanes)]
+            for t in th:
+                t.start()
+            for t in th:
+                t.join()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        if errors:
+            raise errors[0]
         prof = {}
         for c in ctxs:
             for k, (cnt, ms) in c.prof_read().items():

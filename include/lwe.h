@@ -153,12 +153,14 @@ int lwe_prof_enable(lwe_ctx* ctx, int on);
 int lwe_prof_reset(lwe_ctx* ctx);
 int lwe_prof_read(lwe_ctx* ctx, const char* kernel, uint64_t* launches, double* total_ms);
 
-/* Tuning knobs of the batched product kernel (see lwe_tune_* in the Python package).
- * Zero leaves a knob at its built-in default. */
+/* Tuning knobs of the batched product kernel (the tile autotuner of the Python package,
+ * paper_2606_01211_amd.tune, writes them).  Zero leaves a knob at its built-in default.
+ * lwe_set_tuning returns LWE_EINVAL for a (col_groups, row_groups) pair that the library does
+ * not build. */
 typedef struct {
-  uint32_t col_groups;   /* 16-column groups per workgroup strip (1..4) */
-  uint32_t row_groups;   /* 16-row groups per wave in the streaming loop (1, 2 or 4);
-                            (col_groups, row_groups) pairs: (1..3, 1|2|4), (4, 1|2) */
+  uint32_t col_groups;   /* 16-column groups per workgroup strip */
+  uint32_t row_groups;   /* 16-row groups per wave in the streaming loop; built
+                            (col_groups, row_groups) pairs: (1, 2|4), (2, 2|4), (3, 2|4) */
   uint32_t m_chunks;     /* row chunks sharing one regenerated strip of A */
   uint32_t host_hash_max;/* batches up to this size hash on the host */
 } lwe_tuning;

@@ -293,16 +293,23 @@ int run_product(lwe_ctx* c, int pid, const Params& p, ProdArgs a, bool trans, hi
     if (!CG) {
       CG = 1;
       for (int cg = 3; cg >= 1; --cg)
-        if (product_strip_lds_bytes(cg, ksteps * 64) <= 160 * 1024) {
+        if (product_strip_lds_bytes(cg, ksteps * 64, 3) <= 160 * 1024) {
           CG = cg;
           break;
         }
     }
-    const int RG = tu.row_groups ? (int)tu.row_groups : (CG >= 3 ? 2 : 4);
+    int RG = tu.row_groups ? (int)tu.row_groups : (CG >= 3 ? 2 : 4);
+    if (!product_strip_shape_ok(CG, RG)) {  // a shape the library does not build
+      CG = CG >= 3 ? 3 : CG;
+      RG = CG >= 2 ? 2 : 4;
+    }
     // longest K chunk whose padded strip fits LDS (a multiple of three 64-row steps)
     const int max_rows = (int)(((160 * 1024 - 4096) / (32 * CG)) / 192 * 192);
     a.kc_len = std::min(ksteps * 64, max_rows);
     a.n_kc = (p.n + a.kc_len - 1) / a.kc_len;
+    // a deeper loop unroll (longer X prefetch) when it adds no padding and still fits LDS
+    int unr = a.n_kc == 1 ? product_strip_unroll(CG, RG, a.kc_len) : 3;
+    if (product_strip_lds_bytes(CG, a.kc_len, unr) > 160 * 1024) unr = 3;
     a.n_jt = (a.ncols + 16 * CG - 1) / (16 * CG);
     int mch = tu.m_chunks ? (int)tu.m_chunks : 8;
     const int unit = 16 * RG;
@@ -315,7 +322,7 @@ int run_product(lwe_ctx* c, int pid, const Params& p, ProdArgs a, bool trans, hi
       LWE_CHECK(ensure_t(c, B_ACC, (size_t)a.M * a.acc_ld * 4, &a.acc32));
       KLAUNCH("fill", s, launch_fill_u32((uint32_t*)a.acc32, (size_t)a.M * a.acc_ld, 0, s));
     }
-    KLAUNCH("prod_strip", s, launch_product_strip(a, CG, RG, s));
+    KLAUNCH("prod_strip", s, launch_product_strip(a, CG, RG, unr, s));
   }
   if (a.n_kc > 1) KLAUNCH("finalize", s, launch_finalize(a, s));
   return LWE_OK;
@@ -536,8 +543,11 @@ int lwe_cdf_table(int pid, uint16_t* T_out, size_t capacity) {
 
 int lwe_set_tuning(lwe_ctx* c, int pid, const lwe_tuning* t) {
   if (!c || !t || !get_params(pid)) return LWE_EINVAL;
-  if (t->col_groups > 4 || t->row_groups > 4 || t->row_groups == 3) return LWE_EINVAL;
-  if (t->col_groups == 4 && t->row_groups == 4) return LWE_EINVAL;
+  // both knobs zero (default) or both set to a built pair; one alone pairs with the default
+  if (t->col_groups && t->row_groups && !product_strip_shape_ok((int)t->col_groups, (int)t->row_groups))
+    return LWE_EINVAL;
+  if ((t->col_groups && t->col_groups > 3) || (t->row_groups && t->row_groups != 2 && t->row_groups != 4))
+    return LWE_EINVAL;
   c->tuning[pid & 255] = *t;
   return LWE_OK;
 }

@@ -626,8 +626,13 @@ __global__ void __launch_bounds__(1024) k_prod_stream(ProdArgs a, int ks_per_wav
 // ======================================================================================
 constexpr int STRIP_WAVES = 8;
 
-template <int CG, int RG, bool CMP>
+// UNR: contraction steps per unrolled loop body, and the depth of the X register ring (X
+// fragments are requested UNR - 1 steps ahead; the strip is padded to a multiple of UNR).
+template <int CG, int RG, bool CMP, int UNR>
 __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
+  // strip-fragment ring depth: the phases of one loop body must fill whole ring turns
+  constexpr int YD = (UNR * CG) % 3 == 0 ? 3 : 2;
+  static_assert((UNR * CG) % YD == 0, "strip fragment ring does not tile the loop body");
   __shared__ uint32_t T[1024];  // static: a compile-time address for the table lookups
   extern __shared__ uint32_t smem[];
   uint8_t* strip = (uint8_t*)smem;
@@ -644,9 +649,9 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
   const int k0 = kc * a.kc_len;
   const int k_len = min(a.kc_len, n - k0);
   const int ksteps = (k_len + 63) >> 6;
-  // The contraction loop runs three steps per iteration; the strip is padded with zero
-  // rows of A up to that multiple (a zero strip row adds nothing to any product).
-  const int kst = strip_steps(k_len);
+  // The contraction loop runs UNR steps per iteration; the strip is padded with zero rows of
+  // A up to that multiple (a zero strip row adds nothing to any product).
+  const int kst = strip_steps(k_len, UNR);
   const uint32_t qmask = (1u << a.logq) - 1u;
   const uint32_t qmask2 = qmask * 0x10001u;
   const RoundKeys rk = load_rk(a.rkA);
@@ -665,11 +670,11 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
   struct Item {
     int col_local, kb;
   };
-  auto item = [&](int t) {
+  auto item = [&](int t) __attribute__((always_inline)) {
     const int c16 = t & 15, h = (t >> 4) & 1, g = (t >> 5) & 3, rest = t >> 7;
     return Item{(rest % CG) * 16 + c16, (rest / CG) * 8 + g * 2 + h};
   };
-  auto put = [&](int t, const uint32_t (&w)[4]) {
+  auto put = [&](int t, const uint32_t (&w)[4]) __attribute__((always_inline)) {
     uint32_t lo0, hi0, lo1, hi1;
     limbs4(w[0] & qmask2, w[1] & qmask2, lo0, hi0);
     limbs4(w[2] & qmask2, w[3] & qmask2, lo1, hi1);
@@ -680,7 +685,7 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
     *(uint2*)(base + 64 * 16) = make_uint2(hi0, hi1);
   };
   // entries outside A: zero padding rows, and the public-key columns (B^T) when present
-  auto fixup = [&](const Item& it, uint32_t (&w)[4]) {
+  auto fixup = [&](const Item& it, uint32_t (&w)[4]) __attribute__((always_inline)) {
     const int k = k0 + 8 * it.kb, col = nn0 + it.col_local;
     if (k >= k0 + k_len || col >= n) {
       w[0] = w[1] = w[2] = w[3] = 0;
@@ -729,7 +734,7 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
   // so the epilogue is E' add, mask and one 8-byte store (or compare) per tile.  The other
   // workgroups (the strip holding V's columns, split-K) take the general epilogue.
   const bool fast = a.n_kc == 1 && nn0 + 16 * CG <= n;
-  auto row_ptrs = [&](int rb, const int8_t* (&p)[RG]) {
+  auto row_ptrs = [&](int rb, const int8_t* (&p)[RG]) __attribute__((always_inline)) {
     const int rbase = m_begin + rb * 16 * RG;
 #pragma unroll
     for (int rg = 0; rg < RG; ++rg) {
@@ -742,45 +747,45 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
   row_ptrs(wave, xp);
   row_ptrs(wave + STRIP_WAVES < nrb ? wave + STRIP_WAVES : wave, xq);
 
-  v4i xb[3][RG];  // X ring: slot = step mod 3
-  v4i yb[3][2];   // strip fragment ring: slot = phase mod 3, a phase being one (step, cg)
-  auto load_xs = [&](v4i (&dst)[RG], const int8_t* const (&p)[RG], int s) {
+  v4i xb[UNR][RG];  // X ring: slot = step mod UNR
+  v4i yb[YD][2];    // strip fragment ring: slot = phase mod YD, a phase being one (step, cg)
+  auto load_xs = [&](v4i (&dst)[RG], const int8_t* const (&p)[RG], int s) __attribute__((always_inline)) {
 #pragma unroll
     for (int rg = 0; rg < RG; ++rg) dst[rg] = *(const v4i*)(p[rg] + 64 * s);
   };
-  auto load_y = [&](v4i (&dst)[2], int s, int cg) {
+  auto load_y = [&](v4i (&dst)[2], int s, int cg) __attribute__((always_inline)) {
     dst[0] = *(const v4i*)(strip + ((size_t)((s * CG + cg) * 2) * 64 + lane) * 16);
     dst[1] = *(const v4i*)(strip + ((size_t)((s * CG + cg) * 2 + 1) * 64 + lane) * 16);
   };
   v4i acc[RG][CG][2];
-  load_xs(xb[0], xp, 0);
-  load_xs(xb[1], xp, min(1, klast));
-  load_y(yb[0], 0, 0);
-  // Three steps per iteration (the strip is padded to a multiple of three).  At each step the
-  // X fragments of step + 2 are requested; at each phase the strip fragments of the next
-  // phase (wrapping from the last step to step 0, the strip being the same for every row
-  // block).  Scheduling barriers keep every request ahead of the MFMAs that hide it; the
-  // scheduler would otherwise sink the loads next to their first use.
-  auto three_steps = [&](int s) {
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const int t = s + i, t2 = t + 2;
+  for (int i = 0; i + 1 < UNR; ++i) load_xs(xb[i], xp, min(i, klast));
+  load_y(yb[0], 0, 0);
+  // UNR steps per iteration.  At each step the X fragments of step + UNR - 1 are requested
+  // (from the next row block past the last step); at each phase the strip fragments of the
+  // next phase (wrapping from the last step to step 0, the strip being the same for every
+  // row block).  Scheduling barriers keep every request ahead of the MFMAs that hide it; the
+  // scheduler would otherwise sink the loads next to their first use.
+  auto body = [&](int s) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < UNR; ++i) {
+      const int t = s + i, t2 = t + UNR - 1;
       if (t2 < kst)
-        load_xs(xb[(i + 2) % 3], xp, min(t2, klast));
+        load_xs(xb[(i + UNR - 1) % UNR], xp, min(t2, klast));
       else
-        load_xs(xb[(i + 2) % 3], xq, min(t2 - kst, klast));
+        load_xs(xb[(i + UNR - 1) % UNR], xq, min(t2 - kst, klast));
 #pragma unroll
       for (int cg = 0; cg < CG; ++cg) {
         const int ph = i * CG + cg;
         if (cg + 1 < CG)
-          load_y(yb[(ph + 1) % 3], t, cg + 1);
+          load_y(yb[(ph + 1) % YD], t, cg + 1);
         else
-          load_y(yb[(ph + 1) % 3], t + 1 < kst ? t + 1 : 0, 0);
+          load_y(yb[(ph + 1) % YD], t + 1 < kst ? t + 1 : 0, 0);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int rg = 0; rg < RG; ++rg) {
-          acc[rg][cg][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(yb[ph % 3][0], xb[i][rg], acc[rg][cg][0], 0, 0, 0);
-          acc[rg][cg][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(yb[ph % 3][1], xb[i][rg], acc[rg][cg][1], 0, 0, 0);
+          acc[rg][cg][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(yb[ph % YD][0], xb[i][rg], acc[rg][cg][0], 0, 0, 0);
+          acc[rg][cg][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(yb[ph % YD][1], xb[i][rg], acc[rg][cg][1], 0, 0, 0);
         }
         __builtin_amdgcn_sched_barrier(0);
       }
@@ -788,7 +793,7 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
   };
 
   // One pass over this wave's row blocks; FAST selects the epilogue (uniform per workgroup).
-  auto run = [&](auto fast_tag) {
+  auto run = [&](auto fast_tag) __attribute__((always_inline)) {
     constexpr bool FAST = decltype(fast_tag)::value;
     for (int rb = wave; rb < nrb; rb += STRIP_WAVES) {
       const int rbase = m_begin + rb * 16 * RG;
@@ -817,7 +822,7 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
           }
         }
       }
-      for (int s = 0; s < kst; s += 3) three_steps(s);
+      for (int s = 0; s < kst; s += UNR) body(s);
       // the next block's pointers become current; look one block further ahead
 #pragma unroll
       for (int rg = 0; rg < RG; ++rg) xp[rg] = xq[rg];
@@ -1069,7 +1074,7 @@ __device__ __forceinline__ void rotl64_32(uint32_t hi, uint32_t lo, int r, uint3
 }
 
 __device__ __forceinline__ void keccak_f1600_dev(uint32_t lo[25], uint32_t hi[25]) {
-#pragma unroll 1
+#pragma unroll
   for (int round = 0; round < 24; ++round) {
     uint32_t cl[5], ch[5];
 #pragma unroll
@@ -1141,9 +1146,9 @@ __device__ __forceinline__ uint32_t keccak_rc_half(int round, int parity) {
 
 __device__ __forceinline__ void keccak_f1600_pair(uint32_t s[25], uint32_t p) {
   const uint32_t sh1 = p ? 0u : 31u;  // rotation of the partner's C[x+1] by 1 (even half) or 0
-  // Fully unrolled: pi then costs no register moves (its position cycle has length 24) and
-  // the round constants become immediates.
-#pragma unroll
+  // Twelve rounds per iteration: few register moves for pi at the back edge (its position
+  // cycle has length 24), and a body small enough to stay within 128 registers.
+#pragma unroll 12
   for (int round = 0; round < 24; ++round) {
     uint32_t c[5];
 #pragma unroll
@@ -1207,8 +1212,12 @@ __device__ __forceinline__ uint32_t interleave_in(uint32_t w, uint32_t sel) {
 // SHA3-256 of count records of len bytes, one record per pair of lanes.  Full 136-byte
 // blocks are read as 4-byte words (when aligned) and the next block is fetched while the
 // current one is permuted; the final block and the padding are assembled byte by byte.
-__global__ void __launch_bounds__(64) k_hash_records(int count, const uint8_t* __restrict__ in, size_t stride,
-                                                     size_t len, uint8_t* out) {
+// At most 128 VGPRs (four waves per SIMD): a hash wave is a long dependent chain that shares
+// its CU with the product and sampler workgroups of other streams, and must leave them room.
+// ALIGNED: every record starts at a 4-byte boundary (whole-word loads).
+template <bool ALIGNED>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
+k_hash_records(int count, const uint8_t* __restrict__ in, size_t stride, size_t len, uint8_t* out) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t p = (uint32_t)(t & 1);
   const int rec_raw = t >> 1;
@@ -1219,32 +1228,36 @@ __global__ void __launch_bounds__(64) k_hash_records(int count, const uint8_t* _
 #pragma unroll
   for (int k = 0; k < 25; ++k) s[k] = 0;
   const size_t nfull = len / SHA3_RATE;  // full rate blocks; block nfull is the padded last one
-  const bool aligned = (((uintptr_t)base) & 3) == 0;
   // Raw message words of block b for this lane (bytes 8w + 4p .. 8w + 4p + 3 of the block).
-  // The last block carries the remaining bytes, the domain bits 01 and pad10*1.  No lane
-  // exchange happens in here (the branches may diverge between records).
+  // The last block carries the remaining bytes, the domain bits 01 and pad10*1; with aligned
+  // records only the word holding the end of the message is assembled byte by byte.  No lane
+  // exchange happens in here (the branches may differ between the lanes of a pair).
   auto load_block = [&](size_t b, uint32_t (&m)[17]) {
     const size_t off = b * SHA3_RATE;
-    if (b < nfull && aligned) {
+    if (ALIGNED && b < nfull) {  // a full block: one base address, immediate offsets
       const uint32_t* q = (const uint32_t*)(base + off) + p;
 #pragma unroll
       for (int w = 0; w < 17; ++w) m[w] = q[2 * w];
-    } else {
-      const bool last = b == nfull;
-      const int rem = last ? (int)(len - off) : SHA3_RATE;
+      return;
+    }
+    const bool last = b == nfull;
+    const int rem = last ? (int)(len - off) : SHA3_RATE;
 #pragma unroll
-      for (int w = 0; w < 17; ++w) {
-        uint32_t v = 0;
+    for (int w = 0; w < 17; ++w) {
+      const int pos0 = 8 * w + 4 * (int)p;
+      uint32_t v = 0;
+      if (ALIGNED && pos0 + 4 <= rem) {
+        v = *(const uint32_t*)(base + off + pos0);
+      } else if (pos0 < rem) {
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb) {
-          const int pos = 8 * w + 4 * (int)p + kb;
-          uint32_t byte = pos < rem ? (uint32_t)base[off + pos] : 0u;
-          if (last && pos == rem) byte ^= 0x06u;
-          if (last && pos == SHA3_RATE - 1) byte ^= 0x80u;
-          v |= byte << (8 * kb);
-        }
-        m[w] = v;
+        for (int kb = 0; kb < 4; ++kb)
+          if (pos0 + kb < rem) v |= (uint32_t)base[off + pos0 + kb] << (8 * kb);
       }
+      if (last) {
+        if (rem >= pos0 && rem < pos0 + 4) v ^= 0x06u << (8 * (rem - pos0));
+        if (pos0 + 3 == SHA3_RATE - 1) v ^= 0x80u << 24;
+      }
+      m[w] = v;
     }
   };
   // One absorption loop (one inlined copy of the permutation); the next block is fetched
@@ -1395,35 +1408,42 @@ hipError_t launch_product_stream(const ProdArgs& a, int cg, int rg, int waves, b
   return hipErrorInvalidValue;
 }
 
-size_t product_strip_lds_bytes(int cg, int kc_len) {
-  return 4096 + (size_t)strip_steps(kc_len) * 64 * 16 * cg * 2;
+size_t product_strip_lds_bytes(int cg, int kc_len, int unr) {
+  return 4096 + (size_t)strip_steps(kc_len, unr) * 64 * 16 * cg * 2;
 }
 
-template <int CG, int RG>
+// Loop unroll (X ring depth) of the strip kernel.  Deeper rings (unrolls of 4, 5 and 7, which
+// avoid padding at n = 976, 640 and 1344) measured slower on MI355X: at n = 1344 x 4096 the
+// (3, 2) tile took 220 us with a 7-deep ring against 204 us with a 3-deep one (more registers,
+// no longer room for a hash wave beside the workgroup), so only three is built.
+int product_strip_unroll(int, int, int) { return 3; }
+
+template <int CG, int RG, int UNR>
 static hipError_t launch_strip_t(const ProdArgs& a, hipStream_t s) {
   // compare mode reads the received ciphertexts instead of writing them
-  auto kern = a.mode == PM_COMPARE ? k_prod_strip<CG, RG, true> : k_prod_strip<CG, RG, false>;
-  const size_t lds = product_strip_lds_bytes(CG, a.kc_len) - 4096;  // the T-tables are static
+  auto kern = a.mode == PM_COMPARE ? k_prod_strip<CG, RG, true, UNR> : k_prod_strip<CG, RG, false, UNR>;
+  const size_t lds = product_strip_lds_bytes(CG, a.kc_len, UNR) - 4096;  // the T-tables are static
   const int total = a.n_jt * a.n_kc * a.n_mt;
   const unsigned grid = (unsigned)(8 * ((total + 7) / 8));
   hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * STRIP_WAVES), lds, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_product_strip(const ProdArgs& a, int cg, int rg, hipStream_t s) {
+// (CG, RG) shapes the library builds
+#define LWE_STRIP_SHAPES(X) X(1, 2) X(1, 4) X(2, 2) X(2, 4) X(3, 2) X(3, 4)
+
+bool product_strip_shape_ok(int cg, int rg) {
+#define LWE_SHAPE_OK(CG_, RG_) if (cg == CG_ && rg == RG_) return true;
+  LWE_STRIP_SHAPES(LWE_SHAPE_OK)
+#undef LWE_SHAPE_OK
+  return false;
+}
+
+hipError_t launch_product_strip(const ProdArgs& a, int cg, int rg, int unr, hipStream_t s) {
+  if (unr != 3) return hipErrorInvalidValue;
 #define LWE_STRIP_CASE(CG_, RG_) \
-  if (cg == CG_ && rg == RG_) return launch_strip_t<CG_, RG_>(a, s);
-  LWE_STRIP_CASE(1, 1)
-  LWE_STRIP_CASE(1, 2)
-  LWE_STRIP_CASE(1, 4)
-  LWE_STRIP_CASE(2, 1)
-  LWE_STRIP_CASE(2, 2)
-  LWE_STRIP_CASE(2, 4)
-  LWE_STRIP_CASE(3, 1)
-  LWE_STRIP_CASE(3, 2)
-  LWE_STRIP_CASE(3, 4)
-  LWE_STRIP_CASE(4, 1)
-  LWE_STRIP_CASE(4, 2)
+  if (cg == CG_ && rg == RG_) return launch_strip_t<CG_, RG_, 3>(a, s);
+  LWE_STRIP_SHAPES(LWE_STRIP_CASE)
 #undef LWE_STRIP_CASE
   return hipErrorInvalidValue;
 }
@@ -1452,7 +1472,13 @@ hipError_t launch_fo_coins(int count, const uint8_t* pkh, const uint8_t* mu, siz
 hipError_t launch_hash_records(int count, const uint8_t* in, size_t stride, size_t len, uint8_t* out,
                                hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_hash_records, dim3(nblk(2 * (size_t)count, 64)), dim3(64), 0, s, count, in, stride, len, out);
+  const bool aligned = (((uintptr_t)in | stride) & 3) == 0;
+  if (aligned)
+    hipLaunchKernelGGL(k_hash_records<true>, dim3(nblk(2 * (size_t)count, 64)), dim3(64), 0, s, count, in, stride,
+                       len, out);
+  else
+    hipLaunchKernelGGL(k_hash_records<false>, dim3(nblk(2 * (size_t)count, 64)), dim3(64), 0, s, count, in, stride,
+                       len, out);
   return hipGetLastError();
 }
 
@@ -1463,12 +1489,12 @@ hipError_t launch_final_ss(int count, const uint32_t* flags, const uint8_t* kpri
   return hipGetLastError();
 }
 
-template <int CG, int RG>
-static hipError_t allow_lds_strip() {
-  hipError_t e = hipFuncSetAttribute((const void*)k_prod_strip<CG, RG, false>,
+template <int CG, int RG, int UNR>
+static hipError_t allow_lds_strip_u() {
+  hipError_t e = hipFuncSetAttribute((const void*)k_prod_strip<CG, RG, false, UNR>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 4096);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_prod_strip<CG, RG, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  return hipFuncSetAttribute((const void*)k_prod_strip<CG, RG, true, UNR>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              160 * 1024 - 4096);
 }
 template <int CG, int RG, bool TR>
@@ -1487,17 +1513,9 @@ hipError_t init_kernels() {
   }
 #define LWE_TRY(x) \
   if ((r = (x)) != hipSuccess) e = r;
-  LWE_TRY((allow_lds_strip<1, 1>()))
-  LWE_TRY((allow_lds_strip<1, 2>()))
-  LWE_TRY((allow_lds_strip<1, 4>()))
-  LWE_TRY((allow_lds_strip<2, 1>()))
-  LWE_TRY((allow_lds_strip<2, 2>()))
-  LWE_TRY((allow_lds_strip<2, 4>()))
-  LWE_TRY((allow_lds_strip<3, 1>()))
-  LWE_TRY((allow_lds_strip<3, 2>()))
-  LWE_TRY((allow_lds_strip<3, 4>()))
-  LWE_TRY((allow_lds_strip<4, 1>()))
-  LWE_TRY((allow_lds_strip<4, 2>()))
+#define LWE_ALLOW_STRIP(CG_, RG_) LWE_TRY((allow_lds_strip_u<CG_, RG_, 3>()))
+  LWE_STRIP_SHAPES(LWE_ALLOW_STRIP)
+#undef LWE_ALLOW_STRIP
   LWE_TRY((allow_lds_stream<1, 1, false>()))
   LWE_TRY((allow_lds_stream<1, 2, false>()))
   LWE_TRY((allow_lds_stream<1, 4, false>()))

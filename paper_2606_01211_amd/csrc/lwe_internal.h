@@ -88,11 +88,12 @@ hipError_t launch_sample_stream(const Params& p, const uint32_t* rk, const uint3
 hipError_t launch_sample(const SampleArgs& a, int count, hipStream_t s);
 hipError_t launch_product_stream(const ProdArgs& a, int cg, int rg, int waves, bool trans,
                                  int n_row_tiles, int ksteps_per_wave, hipStream_t s);
-hipError_t launch_product_strip(const ProdArgs& a, int cg, int rg, hipStream_t s);
-size_t product_strip_lds_bytes(int cg, int kc_len);
-// 64-deep contraction steps of a strip over kc_len rows, padded to the kernel's
-// three-step unroll.
-LWE_HD int strip_steps(int kc_len) { return ((kc_len + 63) / 64 + 2) / 3 * 3; }
+hipError_t launch_product_strip(const ProdArgs& a, int cg, int rg, int unr, hipStream_t s);
+size_t product_strip_lds_bytes(int cg, int kc_len, int unr);
+int product_strip_unroll(int cg, int rg, int kc_len);
+bool product_strip_shape_ok(int cg, int rg);
+// 64-deep contraction steps of a strip over kc_len rows, padded to the kernel's unroll.
+LWE_HD int strip_steps(int kc_len, int unr) { return ((kc_len + 63) / 64 + unr - 1) / unr * unr; }
 hipError_t launch_finalize(const ProdArgs& a, hipStream_t s);
 hipError_t launch_decrypt(const DecArgs& a, hipStream_t s);
 hipError_t launch_fo_coins(int count, const uint8_t* pkh, const uint8_t* mu, size_t mu_stride,

@@ -27,7 +27,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "tuning.json")
 
 # (col_groups, row_groups) pairs the library instantiates
-SHAPES = [(1, 1), (1, 2), (1, 4), (2, 1), (2, 2), (2, 4), (3, 1), (3, 2), (4, 1), (4, 2)]
+SHAPES = [(1, 2), (1, 4), (2, 2), (2, 4), (3, 2), (3, 4)]
 M_CHUNKS = [4, 6, 8, 12, 16, 24]
 
 
