@@ -18,6 +18,7 @@ workload (whose outputs are compared byte for byte with the GPU's).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -247,6 +248,28 @@ def main():
         return r
 
     rooflines = {k: roofline_of(k) for k in work_per_step if k in kern}
+    # HBM traffic per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE passes
+    # (scaled by the same counters over a 1 GiB copy); only while the kernels are those the
+    # counters were taken on.
+    try:
+        here = os.path.dirname(os.path.abspath(__file__))
+        tr = json.load(open(os.path.join(here, "profiles", "traffic.json")))
+        src = open(os.path.join(here, "paper_2606_01211_amd", "csrc", "kernels.hip"), "rb").read()
+        if tr.get("kernels_source_sha256") == hashlib.sha256(src).hexdigest():
+            tk = tr["kernels"]
+            by = {
+                "prod_strip": [tk.get("k_prod_strip<3, 2, false"), tk.get("k_prod_strip<3, 2, true")],
+                "sample": [tk.get("k_sample<6>")],
+                "hash_records": [tk.get("k_hash_records")],
+                "decrypt": [tk.get("k_decrypt")],
+            }
+            for k, ents in by.items():
+                ents = [e for e in ents if e]
+                if k in rooflines and ents and n == 1344 and B == 4096:
+                    rooflines[k]["traffic"] = sum(e["fetch_bytes"] + (e["write_bytes"] or 0) for e in ents) / len(ents)
+                    rooflines[k]["traffic_unit"] = "HBM bytes per launch"
+    except (OSError, ValueError, KeyError):
+        pass
     dominant = max(rooflines, key=lambda k: kern[k]["total_ms"])
     roof = rooflines[dominant]
 
