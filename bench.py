@@ -58,6 +58,10 @@ def parse():
     ap.add_argument("--streams", type=int, default=4,
                     help="independent steps in flight (one library context and HIP stream each); the "
                          "serial rate (one stream) is always measured too")
+    ap.add_argument("--hw-queues", type=int, default=16,
+                    help="HIP hardware queues of this process (GPU_MAX_HW_QUEUES, at most 32): each "
+                         "stream in flight, and each context's second stream, then gets a queue of "
+                         "its own instead of waiting behind another stream's packets")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="budget of the CPU oracle leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -82,6 +86,8 @@ def main():
     args = parse()
     if args.copy_calibration:
         return copy_calibration()
+    # before anything initialises the GPU runtime
+    os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, max(1, args.hw_queues)))
     if args.gpus != 1:
         print("bench.py measures one GPU: the KEM hot path here runs on a single MI355X; "
               "--gpus %d is not supported (every GPU box has one GPU)" % args.gpus, file=sys.stderr)
@@ -318,6 +324,7 @@ def main():
         "bit_exact": bit_exact,
         "batch_latency_ms": {"p50": pct(step_ms, 50), "p99": pct(step_ms, 99)},
         "streams": S,
+        "hw_queues": int(os.environ["GPU_MAX_HW_QUEUES"]),
         "serial": {"value": serial_value, "ms_per_step": 1e3 * wall1 / K,
                    "batch_latency_ms": {"p50": pct(step_ms1, 50), "p99": pct(step_ms1, 99)}},
         "plain": {"value": plain_rate, "unit": "encaps+decaps/s",

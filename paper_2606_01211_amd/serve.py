@@ -22,6 +22,8 @@ from __future__ import annotations
 
 import collections
 import concurrent.futures as cf
+import gc
+import heapq
 import threading
 import time
 from dataclasses import dataclass, field
@@ -96,7 +98,11 @@ class Server:
         self.max_batch = int(max_batch)
         self.clock = clock
         self.footprint = footprint
-        self._queues: Dict[Tuple[int, int, int], collections.deque] = collections.OrderedDict()
+        self._queues: Dict[Tuple[int, int, int], collections.deque] = {}
+        # (arrival of the queue head, sequence, queue key) of every non-empty queue: the
+        # oldest waiting request's queue is the heap minimum
+        self._heads: List[Tuple[float, int, Tuple[int, int, int]]] = []
+        self._seq = 0
         self._cv = threading.Condition()
         self._free_lanes = list(range(backend.lanes()))
         self._reserved = 0
@@ -117,9 +123,19 @@ class Server:
         with self._cv:
             if self._stop:
                 raise RuntimeError("server stopped")
-            self._queues.setdefault((op, n, r.key), collections.deque()).append(r)
+            k = (op, n, r.key)
+            q = self._queues.get(k)
+            if q is None:
+                q = self._queues[k] = collections.deque()
+            if not q:
+                self._push_head(r.arrival, k)
+            q.append(r)
             self._cv.notify_all()
         return r.future
+
+    def _push_head(self, arrival: float, k: Tuple[int, int, int]) -> None:
+        self._seq += 1
+        heapq.heappush(self._heads, (arrival, self._seq, k))
 
     def close(self) -> None:
         with self._cv:
@@ -137,14 +153,16 @@ class Server:
     # ---- scheduler ----
     def _pick_group(self) -> Optional[Tuple[Tuple[int, int, int], List[Request], int]]:
         """Oldest queue head first; as many of its requests as fit the free budget."""
-        best = None
-        for k, q in self._queues.items():
-            if q and (best is None or q[0].arrival < self._queues[best][0].arrival):
-                best = k
-        if best is None:
+        while self._heads:
+            arrival, seq, best = self._heads[0]
+            q = self._queues.get(best)
+            if not q or q[0].arrival != arrival:  # stale entry
+                heapq.heappop(self._heads)
+                continue
+            break
+        else:
             return None
         op, n, key = best
-        q = self._queues[best]
         free = self.budget - self._reserved
         take = min(len(q), self.max_batch)
         while take > 0 and self.footprint(n, op, take) > free:
@@ -152,13 +170,17 @@ class Server:
         if take == 0:
             if self._in_flight == 0 and self.footprint(n, op, 1) > self.budget:
                 # can never fit: fail this request alone
+                heapq.heappop(self._heads)
                 r = q.popleft()
+                if q:
+                    self._push_head(q[0].arrival, best)
                 r.future.set_exception(LweError("request needs more device memory than the budget (LWE_ENOMEM)"))
                 return self._pick_group()
             return None
+        heapq.heappop(self._heads)
         reqs = [q.popleft() for _ in range(take)]
-        if not q:
-            del self._queues[best]
+        if q:
+            self._push_head(q[0].arrival, best)
         return best, reqs, self.footprint(n, op, take)
 
     def _loop(self) -> None:
@@ -297,29 +319,42 @@ def run_load(server: Server, backend: LibraryBackend, qps: float, duration_s: fl
     keys = g.integers(0, keys_per_n, size=count)
     if ct_pool is None:
         ct_pool = prime_ct_pool(backend, ns, keys_per_n)
-    futs = []
-    t0 = server.clock()
+    # every payload is drawn before the clock starts, so the generator only submits
+    payloads = []
     for i in range(count):
-        target = t0 + arrivals[i]
-        while True:
-            now = server.clock()
-            if now >= target:
-                break
-            time.sleep(min(0.0005, target - now))
         op, n, key = int(ops[i]), int(nsel[i]), int(keys[i])
         p = backend.params[n]
         if op == KEYGEN:
             sa, ss_, z = lwe_inputs.keygen_seeds(g, 1)
-            payload = (sa[0].tobytes(), ss_[0].tobytes(), z[0].tobytes())
+            payloads.append((sa[0].tobytes(), ss_[0].tobytes(), z[0].tobytes()))
         elif op == ENCAPS:
-            payload = (lwe_inputs.messages(g, 1, p.mu_bytes)[0].tobytes(),)
+            payloads.append((lwe_inputs.messages(g, 1, p.mu_bytes)[0].tobytes(),))
         else:
             pool = ct_pool[(n, key)]
-            payload = (pool[i % len(pool)],)
-        futs.append((op, server.submit(op, n, key, payload, arrival=target)))
-    for _, f in futs:
-        f.result()
-    t1 = server.clock()
+            payloads.append((pool[i % len(pool)],))
+    # The collector stays off while requests are in flight: a full collection over tens of
+    # thousands of live requests and futures would stall every thread of the server.
+    gc.collect()
+    gc_was = gc.isenabled()
+    gc.disable()
+    try:
+        futs = []
+        t0 = server.clock()
+        for i in range(count):
+            target = t0 + arrivals[i]
+            while True:
+                now = server.clock()
+                if now >= target:
+                    break
+                time.sleep(min(0.0005, target - now))
+            futs.append((int(ops[i]), server.submit(int(ops[i]), int(nsel[i]), int(keys[i]), payloads[i],
+                                                    arrival=target)))
+        for _, f in futs:
+            f.result()
+        t1 = server.clock()
+    finally:
+        if gc_was:
+            gc.enable()
     lat = {OP_NAMES[o]: server.latency_ms(o) for o in (KEYGEN, ENCAPS, DECAPS)}
     allat = server.latency_ms()
     return {
@@ -359,16 +394,23 @@ def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description="Continuous-batching KEM serving benchmark (one GPU)")
     ap.add_argument("--ns", default="640,976,1344,4096")
     ap.add_argument("--keys-per-n", type=int, default=16)
-    ap.add_argument("--lanes", type=int, default=3)
+    ap.add_argument("--lanes", type=int, default=8)
     ap.add_argument("--qps", type=float, default=0.0, help="offered load; 0 = measure capacity first")
     ap.add_argument("--duration", type=float, default=10.0)
     ap.add_argument("--budget-gb", type=float, default=16.0)
     ap.add_argument("--max-batch", type=int, default=1024)
+    ap.add_argument("--hw-queues", type=int, default=16,
+                    help="HIP hardware queues of the process (GPU_MAX_HW_QUEUES, at most 32), so that "
+                         "every lane's stream has a queue of its own")
     args = ap.parse_args(argv)
+    import os
+
+    os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, max(1, args.hw_queues)))  # before the GPU is used
     ns = [int(x) for x in args.ns.split(",")]
     be = LibraryBackend(ns, args.keys_per_n, args.lanes)
     pool = prime_ct_pool(be, ns, args.keys_per_n)
-    out = {"ns": ns, "keys_per_n": args.keys_per_n, "lanes": args.lanes, "mix": [0.2, 0.5, 0.3]}
+    out = {"ns": ns, "keys_per_n": args.keys_per_n, "lanes": args.lanes, "mix": [0.2, 0.5, 0.3],
+           "hw_queues": int(os.environ["GPU_MAX_HW_QUEUES"])}
     budget = int(args.budget_gb * (1 << 30))
     if args.qps <= 0:
         # capacity: a closed burst of requests all arriving at t = 0
