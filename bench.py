@@ -64,6 +64,11 @@ def parse():
                          "its own instead of waiting behind another stream's packets")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="budget of the CPU oracle leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--large", action="store_true",
+                    help="instead of the batched benchmark: one KeyGen, Encaps and Decaps per n in "
+                         "--large-n (device-resident, A regenerated on the fly), timed per phase")
+    ap.add_argument("--large-n", default="8192,16384,32768")
+    ap.add_argument("--large-reps", type=int, default=3)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -82,6 +87,65 @@ def copy_calibration():
     return 0
 
 
+def large(args):
+    """Single KEMs at large n: per-phase wall and device time, and the AES keystream rate of
+    the regeneration of A (n^2/8 blocks per product pass)."""
+    import torch
+
+    import lwe_inputs
+    import paper_2606_01211_amd as L
+
+    dev = torch.device("cuda:0")
+    ctx = L.Context(0)
+    out = {"mode": "large", "data": "synthetic", "runs": {}}
+    for n in [int(x) for x in args.large_n.split(",")]:
+        pid = L.param_id(n)
+        p = L.params(pid)
+        g = lwe_inputs.rng(2, n)
+        pk = torch.empty(p.pk_bytes, dtype=torch.uint8, device=dev)
+        sk = torch.empty(p.sk_bytes, dtype=torch.uint8, device=dev)
+        ct = torch.empty(p.ct_bytes, dtype=torch.uint8, device=dev)
+        ss = torch.empty(32, dtype=torch.uint8, device=dev)
+        ss2 = torch.empty(32, dtype=torch.uint8, device=dev)
+        phases = {"keygen": [], "encaps": [], "decaps": []}
+        dev_ms = {"keygen": [], "encaps": [], "decaps": []}
+        ok = True
+        for rep in range(args.large_reps + 1):
+            sa, ssk, z = lwe_inputs.keygen_seeds(g, 1)
+            mu = torch.from_numpy(lwe_inputs.messages(g, 1, p.mu_bytes)[0]).to(dev)
+            calls = (("keygen", lambda: ctx.keygen(pid, sa[0], ssk[0], z[0], pk, sk)),
+                     ("encaps", lambda: ctx.encaps(pid, pk, mu, ct, ss)),
+                     ("decaps", lambda: ctx.decaps(pid, sk, ct, ss2)))
+            for name, fn in calls:
+                ctx.prof_reset()
+                ctx.prof_enable(True)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                prof = ctx.prof_read()
+                ctx.prof_enable(False)
+                if rep > 0:  # the first repetition grows the context's buffers
+                    phases[name].append(1e3 * (t1 - t0))
+                    dev_ms[name].append(sum(ms for _, ms in prof.values()))
+            ok &= bool(torch.equal(ss, ss2))
+            print("n=%d rep %d done" % (n, rep), file=sys.stderr, flush=True)
+        blocks = n * n // 8
+        r = {"ok": ok, "aes_blocks_per_product": blocks}
+        for name in phases:
+            wall = float(np.median(phases[name]))
+            devt = float(np.median(dev_ms[name]))
+            r[name] = {"wall_ms": wall, "device_ms": devt}
+        # one product pass (A regenerated once) in keygen and encaps, two in decaps (decrypt
+        # reads no A; the re-encryption regenerates it once)
+        r["keystream_GBps_encaps"] = blocks * 16 / (r["encaps"]["device_ms"] * 1e-3) / 1e9
+        out["runs"][str(n)] = r
+    ctx.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -92,6 +156,8 @@ def main():
         print("bench.py measures one GPU: the KEM hot path here runs on a single MI355X; "
               "--gpus %d is not supported (every GPU box has one GPU)" % args.gpus, file=sys.stderr)
         return 2
+    if args.large:
+        return large(args)
     import torch
 
     import lwe_inputs
