@@ -97,10 +97,11 @@ def _keypair(orc, op, g):
 
 
 @pytest.mark.parametrize("n", [200, 640, 976, 1344])
-@pytest.mark.parametrize("count", [1, 3, 40, 300])
+@pytest.mark.parametrize("count", [1, 3, 33, 40, 300])
 def test_encrypt(ctx, orc, n, count):
-    """B' = S'A + E' and V = S'B + E'' + enc(mu) (Alg. 2) for explicit coins; count 300 takes
-    the strip (batched) product kernel, smaller counts the streaming one."""
+    """B' = S'A + E' and V = S'B + E'' + enc(mu) (Alg. 2) for explicit coins; counts from 32
+    take the strip (batched) product kernel, smaller ones the streaming one.  33 instances are
+    264 rows: the last row block and the last row chunk of the strip kernel are ragged."""
     lp, op = _pair(orc, n)
     g = lwe_inputs.rng(0, 1400 + n + count)
     pk, _ = _keypair(orc, op, g)
@@ -307,3 +308,56 @@ def test_large_n_sampled(ctx, orc, n):
     bad[5] ^= 4
     ctx.decaps(lp.pid, sk, bad, ss2)
     assert ss2.tobytes() == H(zz + H(bad.tobytes()))
+
+
+@pytest.mark.parametrize("n", [640, 1344])
+def test_decaps_strip_tampered(ctx, orc, n):
+    """Decaps of 64 ciphertexts (512 rows: the strip kernel in compare mode) made by the
+    oracle, two thirds of them tampered on instances of both parities (two instances share a
+    16-row MFMA tile) in rows 0, 3 and 7 of B', in its first and last column, and in V; every
+    shared secret equals the oracle's decapsulation (Alg. 5, implicit rejection)."""
+    lp, op = _pair(orc, n)
+    g = lwe_inputs.rng(0, 1800 + n)
+    pk, sk = _keypair(orc, op, g)
+    base_mus = lwe_inputs.messages(g, 8, op.mu_bytes)
+    base = [orc.kem_encaps(op, pk, base_mus[i].tobytes())[0] for i in range(8)]
+    count = 64
+    bp = 16 * n  # bytes of B'
+    spots = [0, 2 * (n - 1) + 1, 2 * (7 * n), 2 * (7 * n + n - 1) + 1, bp, bp + 127, 2 * (3 * n + n // 2)]
+    cts = np.zeros((count, op.ct_bytes), np.uint8)
+    tampered = set()
+    for k in range(count):
+        c = bytearray(base[k % 8])
+        if k % 3 != 0:
+            c[spots[k % len(spots)]] ^= 1 << (k % 8)
+            tampered.add(k)
+        cts[k] = np.frombuffer(bytes(c), np.uint8)
+    ss = np.zeros((count, 32), np.uint8)
+    say("decaps strip tampered", n)
+    ctx.decaps_batch(lp.pid, count, sk, cts, ss)
+    for k in range(count):
+        oss, ok = orc.kem_decaps(op, sk, cts[k].tobytes())
+        assert ok == (k not in tampered), k
+        assert ss[k].tobytes() == oss, k
+
+
+def test_argument_checks(ctx, orc):
+    """A batch of zero is a no-op; one over the maximum (65535) or an unknown parameter id is
+    LWE_EINVAL, returned before any buffer is touched."""
+    lib = L()
+    EINVAL = lib.lwe.LWE_EINVAL
+    lp, op = _pair(orc, 640)
+    g = lwe_inputs.rng(0, 1900)
+    pk, _ = _keypair(orc, op, g)
+    mus = lwe_inputs.messages(g, 1, op.mu_bytes)
+    ct = np.zeros((1, op.ct_bytes), np.uint8)
+    ss = np.zeros((1, 32), np.uint8)
+    ctx.encaps_batch(lp.pid, 0, pk, mus, ct, ss)  # no-op
+    assert not ct.any() and not ss.any()
+    pkb = np.frombuffer(pk, np.uint8).copy()
+    st = ctx._lib.lwe_encaps_batch(ctx._h, lp.pid, 65536, pkb.ctypes.data, mus.ctypes.data, ct.ctypes.data,
+                                   ss.ctypes.data, None)
+    assert st == EINVAL
+    with pytest.raises(lib.LweError) as e:
+        lib.params(250)
+    assert e.value.status == EINVAL
