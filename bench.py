@@ -67,6 +67,9 @@ def parse():
     ap.add_argument("--large", action="store_true",
                     help="instead of the batched benchmark: one KeyGen, Encaps and Decaps per n in "
                          "--large-n (device-resident, A regenerated on the fly), timed per phase")
+    ap.add_argument("--unfused", action="store_true",
+                    help="run the unfused variant (tuning a_source = 1): every call first expands A "
+                         "into device memory and the products read it back instead of regenerating it")
     ap.add_argument("--large-n", default="8192,16384,32768")
     ap.add_argument("--large-reps", type=int, default=3)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -107,8 +110,11 @@ def large(args):
         ct = torch.empty(p.ct_bytes, dtype=torch.uint8, device=dev)
         ss = torch.empty(32, dtype=torch.uint8, device=dev)
         ss2 = torch.empty(32, dtype=torch.uint8, device=dev)
+        if args.unfused:
+            ctx.set_tuning(pid, a_source=1)
         phases = {"keygen": [], "encaps": [], "decaps": []}
         dev_ms = {"keygen": [], "encaps": [], "decaps": []}
+        kern_ms = {"keygen": {}, "encaps": {}, "decaps": {}}
         ok = True
         for rep in range(args.large_reps + 1):
             sa, ssk, z = lwe_inputs.keygen_seeds(g, 1)
@@ -129,17 +135,31 @@ def large(args):
                 if rep > 0:  # the first repetition grows the context's buffers
                     phases[name].append(1e3 * (t1 - t0))
                     dev_ms[name].append(sum(ms for _, ms in prof.values()))
+                    for k, (_, ms) in prof.items():
+                        kern_ms[name].setdefault(k, []).append(ms)
             ok &= bool(torch.equal(ss, ss2))
             print("n=%d rep %d done" % (n, rep), file=sys.stderr, flush=True)
         blocks = n * n // 8
-        r = {"ok": ok, "aes_blocks_per_product": blocks}
+        r = {"ok": ok, "aes_blocks_per_product": blocks, "a_source": "unfused" if args.unfused else "fused"}
         for name in phases:
             wall = float(np.median(phases[name]))
             devt = float(np.median(dev_ms[name]))
-            r[name] = {"wall_ms": wall, "device_ms": devt}
+            r[name] = {"wall_ms": wall, "device_ms": devt,
+                       "kernels_ms": {k: float(np.median(v)) for k, v in kern_ms[name].items()}}
         # one product pass (A regenerated once) in keygen and encaps, two in decaps (decrypt
         # reads no A; the re-encryption regenerates it once)
         r["keystream_GBps_encaps"] = blocks * 16 / (r["encaps"]["device_ms"] * 1e-3) / 1e9
+        if args.unfused:
+            # A (n^2 uint16) written once by the expansion and read once by the product
+            km = r["encaps"]["kernels_ms"]
+            a_bytes = 2 * n * n
+            r["unfused"] = {
+                "A_bytes": a_bytes,
+                "expand_A_ms": km.get("expand_A"),
+                "expand_A_write_GBps": a_bytes / (km["expand_A"] * 1e-3) / 1e9 if km.get("expand_A") else None,
+                "product_ms": km.get("prod_stream"),
+                "product_read_GBps": a_bytes / (km["prod_stream"] * 1e-3) / 1e9 if km.get("prod_stream") else None,
+            }
         out["runs"][str(n)] = r
     ctx.close()
     print(json.dumps(out), flush=True)
@@ -173,6 +193,11 @@ def main():
     ctxs = [L.Context(0) for _ in range(S)]
     streams = [torch.cuda.Stream(device=dev) for _ in range(S)]
     ctx = ctxs[0]
+    if args.unfused:
+        for c in ctxs:
+            t = c.get_tuning(pid)
+            t["a_source"] = 1
+            c.set_tuning(pid, **t)
 
     g = lwe_inputs.rng(3, 0)
     seedA, seedSK, z = lwe_inputs.keygen_seeds(g, W + 2 * K)
@@ -302,6 +327,9 @@ def main():
         # decryption reads B' and V of every ciphertext once
         "decrypt": ("hbm", B * p.ct_bytes),
     }
+    if "expand_A" in kern:
+        # unfused variant: each expansion writes A (n^2 uint16) once
+        work_per_step["expand_A"] = ("hbm", kern["expand_A"]["launches"] / K * 2 * n * n)
 
     def roofline_of(name):
         bound, work = work_per_step[name]
@@ -386,7 +414,8 @@ def main():
         "dtype": "int8",
         "data": "synthetic",
         "config": {"workload": "batched-n%dx%d" % (n, B), "n": n, "logq": p.logq, "B": p.B, "batch": B,
-                   "nbar": 8, "mbar": 8, "step": "keygen + encaps_batch + decaps_batch"},
+                   "nbar": 8, "mbar": 8, "step": "keygen + encaps_batch + decaps_batch",
+                   "A": "expanded once per call (unfused)" if args.unfused else "regenerated in the product (fused)"},
         "bit_exact": bit_exact,
         "batch_latency_ms": {"p50": pct(step_ms, 50), "p99": pct(step_ms, 99)},
         "streams": S,

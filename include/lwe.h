@@ -147,7 +147,7 @@ int lwe_test_sha3(lwe_ctx* ctx, size_t count, size_t len, const uint8_t* in, uin
  * bracketed by a pair of HIP events on the stream it runs on.  lwe_prof_read synchronises
  * the recorded events and returns, for one kernel name ("sample", "prod_strip",
  * "prod_stream", "finalize", "decrypt", "fo_coins", "expand_keys", "hash_records",
- * "final_ss", "fill", "keystream", "sample_stream"), the number of launches and their
+ * "final_ss", "fill", "keystream", "sample_stream", "expand_A"), the number of launches and their
  * summed device time since the last reset. */
 int lwe_prof_enable(lwe_ctx* ctx, int on);
 int lwe_prof_reset(lwe_ctx* ctx);
@@ -156,13 +156,18 @@ int lwe_prof_read(lwe_ctx* ctx, const char* kernel, uint64_t* launches, double* 
 /* Tuning knobs of the batched product kernel (the tile autotuner of the Python package,
  * paper_2606_01211_amd.tune, writes them).  Zero leaves a knob at its built-in default.
  * lwe_set_tuning returns LWE_EINVAL for a (col_groups, row_groups) pair that the library does
- * not build. */
+ * not build, or an a_source other than 0 or 1. */
 typedef struct {
   uint32_t col_groups;   /* 16-column groups per workgroup strip */
   uint32_t row_groups;   /* 16-row groups per wave in the streaming loop; built
                             (col_groups, row_groups) pairs: (1, 2|4), (2, 2|4), (3, 2|4) */
   uint32_t m_chunks;     /* row chunks sharing one regenerated strip of A */
   uint32_t host_hash_max;/* batches up to this size hash on the host */
+  uint32_t a_source;     /* 0: every product regenerates A from its seed inside the kernel
+                            (fused; the default).  1: each call first expands A once into
+                            device memory (n * n * 2 bytes held by the context) and the
+                            product reads it back (unfused; key-generation batches of more
+                            than one instance stay fused).  Results are identical. */
 } lwe_tuning;
 int lwe_set_tuning(lwe_ctx* ctx, int pid, const lwe_tuning* t);
 int lwe_get_tuning(lwe_ctx* ctx, int pid, lwe_tuning* t);

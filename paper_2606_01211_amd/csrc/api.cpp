@@ -19,7 +19,7 @@ constexpr size_t LWE_MAX_BATCH = 65535;
 
 enum BufId {
   B_SEEDA, B_SEEDSK, B_Z, B_RKA, B_RK, B_X, B_E, B_E2, B_COINS, B_KP, B_HCT, B_FLAGS, B_MU2,
-  B_ACC, B_PK, B_SK, B_CT, B_MU, B_SS, B_PKH, B_TEST, B_COUNT
+  B_ACC, B_PK, B_SK, B_CT, B_MU, B_SS, B_PKH, B_TEST, B_AMAT, B_COUNT
 };
 
 struct Buf {
@@ -266,6 +266,14 @@ int run_product(lwe_ctx* c, int pid, const Params& p, ProdArgs a, bool trans, hi
   const int ksteps = (p.n + 63) / 64;
   const lwe_tuning& tu = tuning_of(c, pid);
   const bool strip = !trans && !a.per_inst_A && a.M >= 256;
+  // Unfused variant: expand A once into device memory and let the product read it (one A per
+  // call, so not for key-generation batches, where every instance has its own A).
+  if (tu.a_source == 1 && (!a.per_inst_A || a.M == 8)) {
+    uint16_t* Am;
+    LWE_CHECK(ensure_t(c, B_AMAT, (size_t)p.n * p.n * 2, &Am));
+    KLAUNCH("expand_A", s, launch_expand_A(p, a.rkA, a.T0, 0, (uint32_t)p.n, Am, s));
+    a.Amat = Am;
+  }
   if (!strip) {
     int RG = 1;
     if (!a.per_inst_A) RG = a.M <= 16 ? 1 : (a.M <= 32 ? 2 : 4);
@@ -548,6 +556,7 @@ int lwe_set_tuning(lwe_ctx* c, int pid, const lwe_tuning* t) {
     return LWE_EINVAL;
   if ((t->col_groups && t->col_groups > 3) || (t->row_groups && t->row_groups != 2 && t->row_groups != 4))
     return LWE_EINVAL;
+  if (t->a_source > 1) return LWE_EINVAL;
   c->tuning[pid & 255] = *t;
   return LWE_OK;
 }

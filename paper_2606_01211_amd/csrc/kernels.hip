@@ -277,23 +277,40 @@ __global__ void k_keystream(const uint32_t* __restrict__ rk, const uint32_t* __r
   *(uint4*)(out + 16 * t) = v;
 }
 
-// A[i][j] = keystream word (j n + i) of domain 0 under seedA, masked to logq bits.
-__global__ void k_expand_A(int n, uint32_t qmask2, const uint32_t* __restrict__ rk,
-                           const uint32_t* __restrict__ T0, uint32_t col0, uint32_t ncols,
-                           uint16_t* out) {
-  __shared__ uint32_t T[1024];
-  load_tables(T, T0);
+// A[i][j] = keystream word (j n + i) of domain 0 under seedA, masked to logq bits: AES block
+// b holds column b / (n/8), rows 8 (b mod n/8) .. +7, so block b lands at out + 8 (b - b0).
+// Persistent waves over units of 64 * EXPAND_ILP consecutive blocks, replicated tables.
+constexpr int EXPAND_ILP = 4, EXPAND_WAVES = 8;
+__global__ void __launch_bounds__(64 * EXPAND_WAVES) k_expand_A(uint32_t qmask2, const uint32_t* __restrict__ rk,
+                                                               const uint32_t* __restrict__ T0, uint64_t b0,
+                                                               size_t nblocks, uint16_t* out) {
+  __shared__ uint32_t TR[TR_WORDS];
+  load_tables_rep(TR, T0);
   __syncthreads();
-  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t bpc = (size_t)n / 8;
-  if (t >= (size_t)ncols * bpc) return;
-  const size_t c = t / bpc, kb = t % bpc;
-  const uint64_t b = ((uint64_t)col0 + c) * bpc + kb;
+  const int lane = threadIdx.x & 63;
+  const uint32_t off0 = (uint32_t)(lane & 31) << 2, off2 = off0 + 128;
   const RoundKeys rkv = load_rk(rk);
-  uint32_t o[4];
-  aes_ctr_block(T, rkv, 0u, b, o);
-  uint4 v = make_uint4(o[0] & qmask2, o[1] & qmask2, o[2] & qmask2, o[3] & qmask2);
-  *(uint4*)(out + c * n + 8 * kb) = v;
+  uint32_t rkr[36];
+#pragma unroll
+  for (int i = 0; i < 36; ++i) rkr[i] = rotl32(rkv[4 + i], 24);
+  const size_t per_unit = 64 * EXPAND_ILP;
+  const size_t n_units = (nblocks + per_unit - 1) / per_unit;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const size_t nwaves = (size_t)gridDim.x * EXPAND_WAVES;
+  for (size_t u = (size_t)blockIdx.x * EXPAND_WAVES + wave; u < n_units; u += nwaves) {
+    uint32_t o[EXPAND_ILP][4];
+#pragma unroll
+    for (int j = 0; j < EXPAND_ILP; ++j) {
+      const size_t t = u * per_unit + j * 64 + lane;
+      aes_ctr_block_rep(TR, off0, off2, rkv, rkr, 0u, b0 + (t < nblocks ? t : nblocks - 1), o[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < EXPAND_ILP; ++j) {
+      const size_t t = u * per_unit + j * 64 + lane;
+      if (t < nblocks)
+        *(uint4*)(out + 8 * t) = make_uint4(o[j][0] & qmask2, o[j][1] & qmask2, o[j][2] & qmask2, o[j][3] & qmask2);
+    }
+  }
 }
 
 struct SampTable {
@@ -455,11 +472,12 @@ __device__ __forceinline__ void flag_tile(const ProdArgs& a, int row_base, uint3
 // at once; waves of a workgroup split the K chunk and are reduced through LDS.
 //   grid.x = n_jt * n_kc, grid.y = row tiles (or instances when per_inst_A)
 // ======================================================================================
-template <int CG, int RG, bool TRANS>
+// MAT: read A from the expanded copy a.Amat instead of regenerating it (unfused variant).
+template <int CG, int RG, bool TRANS, bool MAT>
 __global__ void __launch_bounds__(1024) k_prod_stream(ProdArgs a, int ks_per_wave) {
-  // T-tables in static LDS (a compile-time address, so table offsets fold into the LDS
-  // instructions); the reduction / transpose scratch in dynamic LDS.
-  __shared__ uint32_t T[1024];
+  // Lane-replicated T-tables in static LDS (64 KB, conflict-free lookups; none in the unfused
+  // variant); the reduction / transpose scratch in dynamic LDS.
+  __shared__ uint32_t TR[MAT ? 1 : TR_WORDS];
   extern __shared__ uint32_t smem[];
   const int W = blockDim.x >> 6;
   uint32_t* red = smem;                                         // [W][RG][CG][4][64]
@@ -467,13 +485,17 @@ __global__ void __launch_bounds__(1024) k_prod_stream(ProdArgs a, int ks_per_wav
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int jt = blockIdx.x % a.n_jt, kc = blockIdx.x / a.n_jt, mt = blockIdx.y;
   const RoundKeys rk = load_rk(a.rkA + (a.per_inst_A ? (size_t)mt * 44 : 0));
+  uint32_t rkr[36];  // rotr8 of round-key words 4 .. 39 (replicated-table AES)
+#pragma unroll
+  for (int i = 0; i < 36; ++i) rkr[i] = rotl32(rk[4 + i], 24);
+  const uint32_t off0 = (uint32_t)(lane & 31) << 2, off2 = off0 + 128;
   const int n = a.n;
   const int m_begin = mt * a.m_tile, m_end = min(a.M, m_begin + a.m_tile);
   const int nn0 = jt * 16 * CG;
   const uint32_t qmask2 = ((1u << a.logq) - 1u) * 0x10001u;
   const int k_chunk0 = kc * a.kc_len;
 
-  load_tables(T, a.T0);
+  if constexpr (!MAT) load_tables_rep(TR, a.T0);
   __syncthreads();
 
   v4i acc[RG][CG][2];
@@ -504,9 +526,19 @@ __global__ void __launch_bounds__(1024) k_prod_stream(ProdArgs a, int ks_per_wav
         uint32_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         if (kvalid && k < n) {
           if (col < n) {
-            const uint64_t b = ((uint64_t)col * n + k) >> 3;
-            aes_ctr_block(T, rk, 0u, b, w);
-            if (k + 8 < n) aes_ctr_block(T, rk, 0u, b + 1, w + 4);
+            if constexpr (MAT) {
+              const uint16_t* src = a.Amat + (size_t)col * n + k;
+              const uint4 v0 = *(const uint4*)src;
+              w[0] = v0.x; w[1] = v0.y; w[2] = v0.z; w[3] = v0.w;
+              if (k + 8 < n) {
+                const uint4 v1 = *(const uint4*)(src + 8);
+                w[4] = v1.x; w[5] = v1.y; w[6] = v1.z; w[7] = v1.w;
+              }
+            } else {
+              const uint64_t b = ((uint64_t)col * n + k) >> 3;
+              aes_ctr_block_rep(TR, off0, off2, rk, rkr, 0u, b, w);
+              if (k + 8 < n) aes_ctr_block_rep(TR, off0, off2, rk, rkr, 0u, b + 1, w + 4);
+            }
           } else if (col < n + 8 && a.Bt) {
             const uint4 v0 = *(const uint4*)(a.Bt + 2 * ((size_t)(col - n) * n + k));
             w[0] = v0.x; w[1] = v0.y; w[2] = v0.z; w[3] = v0.w;
@@ -532,9 +564,19 @@ __global__ void __launch_bounds__(1024) k_prod_stream(ProdArgs a, int ks_per_wav
         const int i0 = nn0 + cg * 16;
         uint32_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         if (kvalid && j < n && i0 < n) {
-          const uint64_t b = ((uint64_t)j * n + i0) >> 3;
-          aes_ctr_block(T, rk, 0u, b, w);
-          if (i0 + 8 < n) aes_ctr_block(T, rk, 0u, b + 1, w + 4);
+          if constexpr (MAT) {
+            const uint16_t* src = a.Amat + (size_t)j * n + i0;
+            const uint4 v0 = *(const uint4*)src;
+            w[0] = v0.x; w[1] = v0.y; w[2] = v0.z; w[3] = v0.w;
+            if (i0 + 8 < n) {
+              const uint4 v1 = *(const uint4*)(src + 8);
+              w[4] = v1.x; w[5] = v1.y; w[6] = v1.z; w[7] = v1.w;
+            }
+          } else {
+            const uint64_t b = ((uint64_t)j * n + i0) >> 3;
+            aes_ctr_block_rep(TR, off0, off2, rk, rkr, 0u, b, w);
+            if (i0 + 8 < n) aes_ctr_block_rep(TR, off0, off2, rk, rkr, 0u, b + 1, w + 4);
+          }
         }
         uint32_t lo[4], hi[4];
 #pragma unroll
@@ -628,7 +670,9 @@ constexpr int STRIP_WAVES = 8;
 
 // UNR: contraction steps per unrolled loop body, and the depth of the X register ring (X
 // fragments are requested UNR - 1 steps ahead; the strip is padded to a multiple of UNR).
-template <int CG, int RG, bool CMP, int UNR>
+// MAT: fill the strip from the expanded copy a.Amat instead of regenerating it (unfused
+// variant; the loop and epilogue are the same).
+template <int CG, int RG, bool CMP, int UNR, bool MAT>
 __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
   // strip-fragment ring depth: the phases of one loop body must fill whole ring turns
   constexpr int YD = (UNR * CG) % 3 == 0 ? 3 : 2;
@@ -656,10 +700,10 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
   const uint32_t qmask2 = qmask * 0x10001u;
   const RoundKeys rk = load_rk(a.rkA);
 
-  load_tables(T, a.T0);
+  if constexpr (!MAT) load_tables(T, a.T0);
   __syncthreads();
 
-  // ---- regenerate the strip ----
+  // ---- regenerate (or, unfused, copy) the strip ----
   // Item t = one AES block = 8 consecutive contraction rows of one column.  Items are
   // numbered so that consecutive lanes fill consecutive 16-byte fragment slots (conflict-free
   // LDS stores): t = (((s * CG + cg) * 4 + g) * 2 + h) * 16 + c16, where the block covers rows
@@ -705,7 +749,14 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
       tt[j] = t < items ? t : t0;  // past the end: recompute t0, stored once
       const Item it = item(tt[j]);
       const int c = nn0 + it.col_local, k = k0 + 8 * it.kb;
-      aes_ctr_block(T, rk, 0u, ((uint64_t)c * n + k) >> 3, w[j]);
+      if constexpr (MAT) {
+        // entries outside A read a valid one; fixup overwrites them below
+        const int cc = c < n ? c : 0, kk = k < k0 + k_len ? k : k0;
+        const uint4 v = *(const uint4*)(a.Amat + (size_t)cc * n + kk);
+        w[j][0] = v.x; w[j][1] = v.y; w[j][2] = v.z; w[j][3] = v.w;
+      } else {
+        aes_ctr_block(T, rk, 0u, ((uint64_t)c * n + k) >> 3, w[j]);
+      }
     }
 #pragma unroll
     for (int j = 0; j < ILP; ++j) {
@@ -1350,11 +1401,14 @@ hipError_t launch_keystream(const uint32_t* rk, const uint32_t* T0, uint32_t dom
 
 hipError_t launch_expand_A(const Params& p, const uint32_t* rk, const uint32_t* T0, uint32_t col0,
                            uint32_t ncols, uint16_t* out, hipStream_t s) {
-  const size_t work = (size_t)ncols * (p.n / 8);
-  if (work == 0) return hipSuccess;
+  const size_t bpc = (size_t)p.n / 8, nblocks = (size_t)ncols * bpc;
+  if (nblocks == 0) return hipSuccess;
   const uint32_t qmask2 = ((1u << p.logq) - 1u) * 0x10001u;
-  hipLaunchKernelGGL(k_expand_A, dim3(nblk(work, 256)), dim3(256), 0, s, p.n, qmask2, rk, T0, col0,
-                     ncols, out);
+  // two workgroups (64 KB of tables each) per CU at most
+  const size_t units = (nblocks + 64 * EXPAND_ILP - 1) / (64 * EXPAND_ILP);
+  const unsigned grid = (unsigned)std::min<size_t>((units + EXPAND_WAVES - 1) / EXPAND_WAVES, 2 * (size_t)g_num_cus);
+  hipLaunchKernelGGL(k_expand_A, dim3(grid), dim3(64 * EXPAND_WAVES), 0, s, qmask2, rk, T0, (uint64_t)col0 * bpc,
+                     nblocks, out);
   return hipGetLastError();
 }
 
@@ -1383,12 +1437,19 @@ hipError_t launch_sample(const SampleArgs& a, int count, hipStream_t s) {
   return hipGetLastError();
 }
 
+// dynamic LDS limit of the streaming product (the 64 KB of replicated T-tables are static)
+constexpr size_t STREAM_DYN_LDS = 160 * 1024 - TR_WORDS * 4;
+
 template <int CG, int RG, bool TRANS>
 static hipError_t launch_stream_t(const ProdArgs& a, int waves, int n_row_tiles, int ks, hipStream_t s) {
-  // dynamic LDS only (the 4 KB of T-tables are static)
+  // dynamic LDS only (the T-tables are static)
   const size_t lds = (size_t)waves * RG * CG * 256 * 4 + (TRANS ? (size_t)waves * 2 * CG * 1024 : 0);
-  hipLaunchKernelGGL((k_prod_stream<CG, RG, TRANS>), dim3((unsigned)(a.n_jt * a.n_kc), (unsigned)n_row_tiles),
-                     dim3(64 * waves), lds, s, a, ks);
+  if (lds > STREAM_DYN_LDS) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(a.n_jt * a.n_kc), (unsigned)n_row_tiles);
+  if (a.Amat)
+    hipLaunchKernelGGL((k_prod_stream<CG, RG, TRANS, true>), grid, dim3(64 * waves), lds, s, a, ks);
+  else
+    hipLaunchKernelGGL((k_prod_stream<CG, RG, TRANS, false>), grid, dim3(64 * waves), lds, s, a, ks);
   return hipGetLastError();
 }
 
@@ -1401,9 +1462,6 @@ hipError_t launch_product_stream(const ProdArgs& a, int cg, int rg, int waves, b
   LWE_STREAM_CASE(1, 1)
   LWE_STREAM_CASE(1, 2)
   LWE_STREAM_CASE(1, 4)
-  LWE_STREAM_CASE(2, 1)
-  LWE_STREAM_CASE(2, 2)
-  LWE_STREAM_CASE(2, 4)
 #undef LWE_STREAM_CASE
   return hipErrorInvalidValue;
 }
@@ -1421,7 +1479,10 @@ int product_strip_unroll(int, int, int) { return 3; }
 template <int CG, int RG, int UNR>
 static hipError_t launch_strip_t(const ProdArgs& a, hipStream_t s) {
   // compare mode reads the received ciphertexts instead of writing them
-  auto kern = a.mode == PM_COMPARE ? k_prod_strip<CG, RG, true, UNR> : k_prod_strip<CG, RG, false, UNR>;
+  auto kern = a.Amat ? (a.mode == PM_COMPARE ? k_prod_strip<CG, RG, true, UNR, true>
+                                             : k_prod_strip<CG, RG, false, UNR, true>)
+                     : (a.mode == PM_COMPARE ? k_prod_strip<CG, RG, true, UNR, false>
+                                             : k_prod_strip<CG, RG, false, UNR, false>);
   const size_t lds = product_strip_lds_bytes(CG, a.kc_len, UNR) - 4096;  // the T-tables are static
   const int total = a.n_jt * a.n_kc * a.n_mt;
   const unsigned grid = (unsigned)(8 * ((total + 7) / 8));
@@ -1491,16 +1552,23 @@ hipError_t launch_final_ss(int count, const uint32_t* flags, const uint8_t* kpri
 
 template <int CG, int RG, int UNR>
 static hipError_t allow_lds_strip_u() {
-  hipError_t e = hipFuncSetAttribute((const void*)k_prod_strip<CG, RG, false, UNR>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 4096);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_prod_strip<CG, RG, true, UNR>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             160 * 1024 - 4096);
+  const void* kerns[4] = {(const void*)k_prod_strip<CG, RG, false, UNR, false>,
+                          (const void*)k_prod_strip<CG, RG, true, UNR, false>,
+                          (const void*)k_prod_strip<CG, RG, false, UNR, true>,
+                          (const void*)k_prod_strip<CG, RG, true, UNR, true>};
+  for (const void* k : kerns) {
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 4096);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 template <int CG, int RG, bool TR>
 static hipError_t allow_lds_stream() {
-  return hipFuncSetAttribute((const void*)k_prod_stream<CG, RG, TR>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 4096);
+  hipError_t e = hipFuncSetAttribute((const void*)k_prod_stream<CG, RG, TR, false>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)STREAM_DYN_LDS);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_prod_stream<CG, RG, TR, true>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)STREAM_DYN_LDS);
 }
 
 hipError_t init_kernels() {
@@ -1519,15 +1587,9 @@ hipError_t init_kernels() {
   LWE_TRY((allow_lds_stream<1, 1, false>()))
   LWE_TRY((allow_lds_stream<1, 2, false>()))
   LWE_TRY((allow_lds_stream<1, 4, false>()))
-  LWE_TRY((allow_lds_stream<2, 1, false>()))
-  LWE_TRY((allow_lds_stream<2, 2, false>()))
-  LWE_TRY((allow_lds_stream<2, 4, false>()))
   LWE_TRY((allow_lds_stream<1, 1, true>()))
   LWE_TRY((allow_lds_stream<1, 2, true>()))
   LWE_TRY((allow_lds_stream<1, 4, true>()))
-  LWE_TRY((allow_lds_stream<2, 1, true>()))
-  LWE_TRY((allow_lds_stream<2, 2, true>()))
-  LWE_TRY((allow_lds_stream<2, 4, true>()))
 #undef LWE_TRY
   return e;
 }

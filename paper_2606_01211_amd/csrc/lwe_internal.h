@@ -50,6 +50,9 @@ struct ProdArgs {
   const uint8_t* cmp;    // compare: received ct records
   size_t cmp_stride;
   uint32_t* flags;       // compare: per instance, nonzero if any coefficient differs
+  // Unfused variant: A already expanded into device memory, column-major [n][n] uint16
+  // (A[i][j] at Amat[j * n + i], masked to logq bits); null when the product regenerates A.
+  const uint16_t* Amat;
 };
 
 struct SampleArgs {

@@ -34,7 +34,7 @@ EXPORTS = [
 ]
 
 KERNELS = ["sample", "prod_strip", "prod_stream", "finalize", "decrypt", "fo_coins", "expand_keys",
-           "hash_records", "final_ss", "fill", "keystream", "sample_stream"]
+           "hash_records", "final_ss", "fill", "keystream", "sample_stream", "expand_A"]
 
 
 class LweLibraryMissing(ImportError):
@@ -58,7 +58,7 @@ class ParamInfo(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [
         ("col_groups", C.c_uint32), ("row_groups", C.c_uint32), ("m_chunks", C.c_uint32),
-        ("host_hash_max", C.c_uint32),
+        ("host_hash_max", C.c_uint32), ("a_source", C.c_uint32),
     ]
 
 
@@ -264,8 +264,10 @@ class Context:
         return self._lib.lwe_ctx_device_bytes(self._h)
 
     # ---- tuning ----
-    def set_tuning(self, pid: int, col_groups=0, row_groups=0, m_chunks=0, host_hash_max=0):
-        t = Tuning(col_groups, row_groups, m_chunks, host_hash_max)
+    def set_tuning(self, pid: int, col_groups=0, row_groups=0, m_chunks=0, host_hash_max=0, a_source=0):
+        """a_source 0 regenerates A inside the product (fused), 1 expands it once per call
+        into device memory first (unfused)."""
+        t = Tuning(col_groups, row_groups, m_chunks, host_hash_max, a_source)
         _check(self._lib.lwe_set_tuning(self._h, pid, C.byref(t)), "lwe_set_tuning")
 
     def get_tuning(self, pid: int) -> dict:

@@ -54,7 +54,8 @@ def apply_table(ctx, table: dict) -> None:
         except KeyError:
             continue
         ctx.set_tuning(pid, col_groups=t.get("col_groups", 0), row_groups=t.get("row_groups", 0),
-                       m_chunks=t.get("m_chunks", 0), host_hash_max=t.get("host_hash_max", 0))
+                       m_chunks=t.get("m_chunks", 0), host_hash_max=t.get("host_hash_max", 0),
+                       a_source=t.get("a_source", 0))
 
 
 def tune(n: int, batch: int, reps: int = 3, verbose: bool = True) -> dict:
