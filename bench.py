@@ -18,6 +18,7 @@ workload (whose outputs are compared byte for byte with the GPU's).
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -50,8 +51,10 @@ def pct(xs, q):
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=64,
+                    help="timed steps (spread round-robin over the streams; a multiple of --streams keeps "
+                         "the lanes even)")
+    ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--n", type=int, default=1344)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--plain", type=int, default=300, help="plain encaps and decaps calls timed one by one")
@@ -250,6 +253,9 @@ def main():
                 errors.append(e)
 
         torch.cuda.synchronize()
+        # no collector pauses inside the timed region (they stall every feeding thread)
+        gc.collect()
+        gc.disable()
         t0 = time.perf_counter()
         if lanes == 1:
             feed(0)
@@ -261,6 +267,7 @@ def main():
                 t.join()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        gc.enable()
         if errors:
             raise errors[0]
         prof = {}

@@ -186,6 +186,61 @@ __device__ __forceinline__ void aes_ctr_block_rep(const uint32_t* __restrict__ T
 }
 
 // ======================================================================================
+// AES with 32 lane-indexed copies of T0 only (32 KB, conflict-free lookups), for kernels that
+// cannot spare the 64 KB of the T0/T2 copies above: word e*32 + c holds T0[e] for copy
+// c = lane & 31.  A lookup address takes an extract and a shift-or (the 128-byte stride is
+// not a byte move); T1..T3 are rotations of T0:
+//   t_j = T0[s_j.b0] ^ rotl16(T0[s_j+2.b2]) ^ rotl8(T0[s_j+1.b1] ^ rotl16(T0[s_j+3.b3]) ^ rotr8(rk)).
+// ======================================================================================
+constexpr int TQ_WORDS = 256 * 32;
+
+__device__ __forceinline__ void load_tables_q(uint32_t* TQ, const uint32_t* __restrict__ T0) {
+  for (int i = threadIdx.x; i < TQ_WORDS; i += blockDim.x) TQ[i] = T0[i >> 5];
+}
+
+template <int BYTE>
+__device__ __forceinline__ uint32_t q_look(const uint32_t* __restrict__ TQ, uint32_t x, uint32_t off) {
+  return *(const uint32_t*)((const char*)TQ + ((((x >> (8 * BYTE)) & 0xffu) << 7) | off));
+}
+
+// One CTR keystream block (same definition as aes_ctr_block); off = (lane & 31) * 4, rkr as
+// for aes_ctr_block_rep.
+template <class RK>
+__device__ __forceinline__ void aes_ctr_block_q(const uint32_t* __restrict__ TQ, uint32_t off, const RK& rk,
+                                                const uint32_t* rkr, uint32_t dom_le, uint64_t b, uint32_t o[4]) {
+  uint32_t s[4];
+  s[0] = dom_le ^ rk[0];
+  s[1] = rk[1];
+  s[2] = bswap32((uint32_t)(b >> 32)) ^ rk[2];
+  s[3] = bswap32((uint32_t)b) ^ rk[3];
+#pragma unroll
+  for (int r = 1; r < 10; ++r) {
+    uint32_t t[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t a0 = q_look<0>(TQ, s[j], off);
+      const uint32_t a1 = q_look<1>(TQ, s[(j + 1) & 3], off);
+      const uint32_t a2 = q_look<2>(TQ, s[(j + 2) & 3], off);
+      const uint32_t a3 = q_look<3>(TQ, s[(j + 3) & 3], off);
+      t[j] = x3(a0, rotl32(a2, 16), rotl32(x3(a1, rotl32(a3, 16), rkr[4 * (r - 1) + j]), 8));
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s[j] = t[j];
+  }
+  // Final round: S(x) is byte 2 of T0[x].
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t a0 = q_look<0>(TQ, s[j], off);
+    const uint32_t a1 = q_look<1>(TQ, s[(j + 1) & 3], off);
+    const uint32_t a2 = q_look<2>(TQ, s[(j + 2) & 3], off);
+    const uint32_t a3 = q_look<3>(TQ, s[(j + 3) & 3], off);
+    const uint32_t lo = __builtin_amdgcn_perm(a1, a0, 0x0c0c0602u);
+    const uint32_t hi = __builtin_amdgcn_perm(a3, a2, 0x06020c0cu);
+    o[j] = x3(lo, hi, rk[40 + j]);
+  }
+}
+
+// ======================================================================================
 // Limb split: a 16-bit value x (already reduced mod q) equals lo + 256 hi (mod 2^16) with
 // lo = sext8(x & 0xff) and hi = sext8(((x + 0x80) >> 8) & 0xff).  The int8 byte of lo is the
 // low byte of x itself.
@@ -670,14 +725,17 @@ constexpr int STRIP_WAVES = 8;
 
 // UNR: contraction steps per unrolled loop body, and the depth of the X register ring (X
 // fragments are requested UNR - 1 steps ahead; the strip is padded to a multiple of UNR).
-// MAT: fill the strip from the expanded copy a.Amat instead of regenerating it (unfused
-// variant; the loop and epilogue are the same).
-template <int CG, int RG, bool CMP, int UNR, bool MAT>
+// TAB: where the strip comes from.  0: the expanded copy a.Amat (unfused variant; the loop
+// and epilogue are the same); 1: AES with the 4 KB tables; 2: AES with the 32 KB
+// conflict-free tables (when they fit beside the strip).
+template <int CG, int RG, bool CMP, int UNR, int TAB>
 __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
+  constexpr bool MAT = TAB == 0;
   // strip-fragment ring depth: the phases of one loop body must fill whole ring turns
   constexpr int YD = (UNR * CG) % 3 == 0 ? 3 : 2;
   static_assert((UNR * CG) % YD == 0, "strip fragment ring does not tile the loop body");
-  __shared__ uint32_t T[1024];  // static: a compile-time address for the table lookups
+  // static: a compile-time address for the table lookups
+  __shared__ uint32_t T[TAB == 2 ? TQ_WORDS : (TAB == 1 ? 1024 : 1)];
   extern __shared__ uint32_t smem[];
   uint8_t* strip = (uint8_t*)smem;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -699,8 +757,13 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
   const uint32_t qmask = (1u << a.logq) - 1u;
   const uint32_t qmask2 = qmask * 0x10001u;
   const RoundKeys rk = load_rk(a.rkA);
+  uint32_t rkr[36];  // rotr8 of round-key words 4 .. 39 (conflict-free table AES)
+#pragma unroll
+  for (int i = 0; i < 36; ++i) rkr[i] = rotl32(rk[4 + i], 24);
+  const uint32_t qoff = (uint32_t)(lane & 31) << 2;
 
-  if constexpr (!MAT) load_tables(T, a.T0);
+  if constexpr (TAB == 1) load_tables(T, a.T0);
+  if constexpr (TAB == 2) load_tables_q(T, a.T0);
   __syncthreads();
 
   // ---- regenerate (or, unfused, copy) the strip ----
@@ -754,8 +817,10 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
         const int cc = c < n ? c : 0, kk = k < k0 + k_len ? k : k0;
         const uint4 v = *(const uint4*)(a.Amat + (size_t)cc * n + kk);
         w[j][0] = v.x; w[j][1] = v.y; w[j][2] = v.z; w[j][3] = v.w;
-      } else {
+      } else if constexpr (TAB == 1) {
         aes_ctr_block(T, rk, 0u, ((uint64_t)c * n + k) >> 3, w[j]);
+      } else {
+        aes_ctr_block_q(T, qoff, rk, rkr, 0u, ((uint64_t)c * n + k) >> 3, w[j]);
       }
     }
 #pragma unroll
@@ -1478,12 +1543,14 @@ int product_strip_unroll(int, int, int) { return 3; }
 
 template <int CG, int RG, int UNR>
 static hipError_t launch_strip_t(const ProdArgs& a, hipStream_t s) {
-  // compare mode reads the received ciphertexts instead of writing them
-  auto kern = a.Amat ? (a.mode == PM_COMPARE ? k_prod_strip<CG, RG, true, UNR, true>
-                                             : k_prod_strip<CG, RG, false, UNR, true>)
-                     : (a.mode == PM_COMPARE ? k_prod_strip<CG, RG, true, UNR, false>
-                                             : k_prod_strip<CG, RG, false, UNR, false>);
   const size_t lds = product_strip_lds_bytes(CG, a.kc_len, UNR) - 4096;  // the T-tables are static
+  // the conflict-free tables when they fit beside the strip, else the 4 KB ones
+  const int tab = a.Amat ? 0 : (lds + TQ_WORDS * 4 <= 160 * 1024 ? 2 : 1);
+  // compare mode reads the received ciphertexts instead of writing them
+  const bool cmp = a.mode == PM_COMPARE;
+  auto kern = tab == 0 ? (cmp ? k_prod_strip<CG, RG, true, UNR, 0> : k_prod_strip<CG, RG, false, UNR, 0>)
+            : tab == 1 ? (cmp ? k_prod_strip<CG, RG, true, UNR, 1> : k_prod_strip<CG, RG, false, UNR, 1>)
+                       : (cmp ? k_prod_strip<CG, RG, true, UNR, 2> : k_prod_strip<CG, RG, false, UNR, 2>);
   const int total = a.n_jt * a.n_kc * a.n_mt;
   const unsigned grid = (unsigned)(8 * ((total + 7) / 8));
   hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * STRIP_WAVES), lds, s, a);
@@ -1552,12 +1619,15 @@ hipError_t launch_final_ss(int count, const uint32_t* flags, const uint8_t* kpri
 
 template <int CG, int RG, int UNR>
 static hipError_t allow_lds_strip_u() {
-  const void* kerns[4] = {(const void*)k_prod_strip<CG, RG, false, UNR, false>,
-                          (const void*)k_prod_strip<CG, RG, true, UNR, false>,
-                          (const void*)k_prod_strip<CG, RG, false, UNR, true>,
-                          (const void*)k_prod_strip<CG, RG, true, UNR, true>};
-  for (const void* k : kerns) {
-    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 4096);
+  const void* kerns[6] = {(const void*)k_prod_strip<CG, RG, false, UNR, 0>,
+                          (const void*)k_prod_strip<CG, RG, true, UNR, 0>,
+                          (const void*)k_prod_strip<CG, RG, false, UNR, 1>,
+                          (const void*)k_prod_strip<CG, RG, true, UNR, 1>,
+                          (const void*)k_prod_strip<CG, RG, false, UNR, 2>,
+                          (const void*)k_prod_strip<CG, RG, true, UNR, 2>};
+  for (int i = 0; i < 6; ++i) {
+    const int dyn = 160 * 1024 - (i >= 4 ? TQ_WORDS * 4 : 4096);
+    hipError_t e = hipFuncSetAttribute(kerns[i], hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
