@@ -355,6 +355,16 @@ def main():
         return r
 
     rooflines = {k: roofline_of(k) for k in work_per_step if k in kern}
+    # AES keystream rates.  The sampler's blocks per step are in its work above; the strip
+    # product regenerates A once per row chunk (the regeneration factor) when fused.
+    if "sample" in rooflines:
+        blocks = 2 * n + 2 * B * (2 * n + 8)
+        rooflines["sample"]["keystream_GBps"] = blocks * 16 / (kern["sample"]["total_ms"] * 1e-3 / K) / 1e9
+    if "prod_strip" in rooflines:
+        mch = ctx.get_tuning(pid)["m_chunks"] or 8
+        fused = not args.unfused
+        rooflines["prod_strip"]["A_regeneration_factor"] = mch if fused else 0
+        rooflines["prod_strip"]["aes_blocks_per_launch"] = mch * n * n // 8 if fused else 0
     # HBM traffic per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE passes
     # (scaled by the same counters over a 1 GiB copy); only while the kernels are those the
     # counters were taken on.
