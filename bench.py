@@ -51,20 +51,21 @@ def pct(xs, q):
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=64,
+    ap.add_argument("--steps", type=int, default=128,
                     help="timed steps (spread round-robin over the streams; a multiple of --streams keeps "
                          "the lanes even)")
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--n", type=int, default=1344)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--plain", type=int, default=300, help="plain encaps and decaps calls timed one by one")
-    ap.add_argument("--streams", type=int, default=4,
+    ap.add_argument("--streams", type=int, default=8,
                     help="independent steps in flight (one library context and HIP stream each); the "
                          "serial rate (one stream) is always measured too")
-    ap.add_argument("--hw-queues", type=int, default=16,
-                    help="HIP hardware queues of this process (GPU_MAX_HW_QUEUES, at most 32): each "
-                         "stream in flight, and each context's second stream, then gets a queue of "
-                         "its own instead of waiting behind another stream's packets")
+    ap.add_argument("--hw-queues", type=int, default=0,
+                    help="HIP hardware queues of this process (GPU_MAX_HW_QUEUES, at most 32; default "
+                         "2 * streams + 2): each step in flight runs on its context's two streams, and "
+                         "each of them then gets a queue of its own instead of waiting behind another "
+                         "stream's packets")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="budget of the CPU oracle leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--large", action="store_true",
@@ -174,7 +175,8 @@ def main():
     if args.copy_calibration:
         return copy_calibration()
     # before anything initialises the GPU runtime
-    os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, max(1, args.hw_queues)))
+    hwq = args.hw_queues if args.hw_queues > 0 else 2 * max(1, args.streams) + 2
+    os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, max(1, hwq)))
     if args.gpus != 1:
         print("bench.py measures one GPU: the KEM hot path here runs on a single MI355X; "
               "--gpus %d is not supported (every GPU box has one GPU)" % args.gpus, file=sys.stderr)
@@ -194,7 +196,9 @@ def main():
     K, W = args.steps, args.warmup
     S = max(1, args.streams)
     ctxs = [L.Context(0) for _ in range(S)]
-    streams = [torch.cuda.Stream(device=dev) for _ in range(S)]
+    # each lane runs on its context's own stream (the context's second stream overlaps the
+    # decapsulation hash): two streams per lane, each on a hardware queue of its own
+    streams = [torch.cuda.ExternalStream(c.stream_handle, device=dev) for c in ctxs]
     ctx = ctxs[0]
     if args.unfused:
         for c in ctxs:

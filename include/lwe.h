@@ -77,6 +77,13 @@ int lwe_ctx_create(lwe_ctx** out, int device, size_t hbm_budget_bytes);
 void lwe_ctx_destroy(lwe_ctx* ctx);
 /* Device working memory currently held by the context, in bytes. */
 size_t lwe_ctx_device_bytes(const lwe_ctx* ctx);
+/* The context's own HIP stream (a hipStream_t; owned by the context, valid until
+ * lwe_ctx_destroy).  Calls given a NULL stream run on it and return once it has finished;
+ * a caller may also pass it explicitly to run asynchronously, so that each context's work
+ * uses only the context's two streams (this one and the internal one that overlaps the
+ * decapsulation hash), which keeps HIP's stream-to-hardware-queue mapping predictable when
+ * several contexts run concurrently.  NULL for a NULL context. */
+void* lwe_ctx_stream(lwe_ctx* ctx);
 const char* lwe_strerror(int status);
 
 /* Parameter registry: id of the set for lattice dimension n, or a negative lwe_status. */

@@ -477,6 +477,7 @@ void lwe_ctx_destroy(lwe_ctx* c) {
 }
 
 size_t lwe_ctx_device_bytes(const lwe_ctx* c) { return c ? c->held + 1024 : 0; }
+void* lwe_ctx_stream(lwe_ctx* c) { return c ? (void*)c->own : nullptr; }
 
 int lwe_prof_enable(lwe_ctx* c, int on) {
   if (!c) return LWE_EINVAL;

@@ -249,7 +249,9 @@ class LibraryBackend(Backend):
         self.L = lwe
         self.dev = torch.device("cuda:%d" % device)
         self._lanes = [lwe.Context(device, lane_budget) for _ in range(lanes)]
-        self._streams = [torch.cuda.Stream(device=self.dev) for _ in range(lanes)]
+        # each lane runs on its context's own stream; with the context's second stream (the
+        # decapsulation hash) that is two streams per lane, each given a hardware queue
+        self._streams = [c.stream_handle for c in self._lanes]
         self.pids = {n: lwe.param_id(n) for n in ns}
         self.params = {n: lwe.params(self.pids[n]) for n in ns}
         self.keys: Dict[int, List[Tuple]] = {}
@@ -274,7 +276,7 @@ class LibraryBackend(Backend):
         return self.keys[n][key][2], self.keys[n][key][3]
 
     def run(self, lane: int, op: int, n: int, key: int, payloads: List[Tuple]) -> List:
-        ctx, st = self._lanes[lane], self._streams[lane].cuda_stream
+        ctx, st = self._lanes[lane], self._streams[lane]
         p = self.params[n]
         c = len(payloads)
         if op == KEYGEN:
@@ -399,13 +401,14 @@ def main(argv=None) -> int:
     ap.add_argument("--duration", type=float, default=10.0)
     ap.add_argument("--budget-gb", type=float, default=16.0)
     ap.add_argument("--max-batch", type=int, default=1024)
-    ap.add_argument("--hw-queues", type=int, default=16,
-                    help="HIP hardware queues of the process (GPU_MAX_HW_QUEUES, at most 32), so that "
-                         "every lane's stream has a queue of its own")
+    ap.add_argument("--hw-queues", type=int, default=0,
+                    help="HIP hardware queues of the process (GPU_MAX_HW_QUEUES, at most 32; default "
+                         "2 * lanes + 2), so that both streams of every lane have a queue of their own")
     args = ap.parse_args(argv)
     import os
 
-    os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, max(1, args.hw_queues)))  # before the GPU is used
+    hwq = args.hw_queues if args.hw_queues > 0 else 2 * max(1, args.lanes) + 2
+    os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, max(1, hwq)))  # before the GPU is used
     ns = [int(x) for x in args.ns.split(",")]
     be = LibraryBackend(ns, args.keys_per_n, args.lanes)
     pool = prime_ct_pool(be, ns, args.keys_per_n)
