@@ -361,3 +361,72 @@ def test_argument_checks(ctx, orc):
     with pytest.raises(lib.LweError) as e:
         lib.params(250)
     assert e.value.status == EINVAL
+
+
+def test_full_batch_4096_sampled(ctx, orc):
+    """The benchmark's batched configuration at full size: 4096 encapsulations at n = 1344 in
+    one call (strip product with the tuned tile shape), checked against the oracle at sampled
+    instances (both ends, both parities of a 16-row MFMA tile, row-chunk boundaries), then all
+    4096 decapsulated on the device (KEM invariant) and a sample of them by the oracle."""
+    lp, op = _pair(orc, 1344)
+    g = lwe_inputs.rng(0, 4096)
+    pk, sk = _keypair(orc, op, g)
+    count = 4096
+    mus = lwe_inputs.messages(g, count, op.mu_bytes)
+    ct = np.zeros((count, op.ct_bytes), np.uint8)
+    ss = np.zeros((count, 32), np.uint8)
+    say("full batch encaps 4096")
+    ctx.encaps_batch(lp.pid, count, pk, mus, ct, ss)
+    for i in [0, 1, 511, 512, 2047, 2048, 3071, 4095]:
+        oct_, oss = orc.kem_encaps(op, pk, mus[i].tobytes())
+        assert ct[i].tobytes() == oct_ and ss[i].tobytes() == oss, i
+    ss2 = np.zeros((count, 32), np.uint8)
+    say("full batch decaps 4096")
+    ctx.decaps_batch(lp.pid, count, sk, ct, ss2)
+    assert np.array_equal(ss2, ss)
+    for i in [5, 4094]:
+        oss, ok = orc.kem_decaps(op, sk, ct[i].tobytes())
+        assert ok and ss2[i].tobytes() == oss
+
+
+def test_context_stream_lanes(orc):
+    """Two contexts driven from device buffers on their own streams (lwe_ctx_stream), as the
+    benchmark and the server run their lanes, concurrently: each lane's outputs equal the
+    oracle's and do not depend on the other lane running."""
+    import torch
+
+    lib = L()
+    lp, op = _pair(orc, 640)
+    g = lwe_inputs.rng(0, 2100)
+    pk, sk = _keypair(orc, op, g)
+    count = 96
+    dev = torch.device("cuda:0")
+    ctxs = [lib.Context(0), lib.Context(0)]
+    try:
+        handles = [c.stream_handle for c in ctxs]
+        assert all(handles) and handles[0] != handles[1]
+        streams = [torch.cuda.ExternalStream(h, device=dev) for h in handles]
+        d_pk = torch.from_numpy(np.frombuffer(pk, np.uint8).copy()).to(dev)
+        d_sk = torch.from_numpy(np.frombuffer(sk, np.uint8).copy()).to(dev)
+        mus = [lwe_inputs.messages(g, count, op.mu_bytes) for _ in range(2)]
+        d_mus = [torch.from_numpy(m).to(dev) for m in mus]
+        outs = [tuple(torch.empty(shape, dtype=torch.uint8, device=dev)
+                      for shape in ((count, op.ct_bytes), (count, 32), (count, 32))) for _ in range(2)]
+        torch.cuda.synchronize()  # inputs in place before either lane's stream reads them
+        for lane in range(2):  # both lanes in flight at once
+            d_ct, d_ss, d_ss2 = outs[lane]
+            with torch.cuda.stream(streams[lane]):
+                ctxs[lane].encaps_batch(lp.pid, count, d_pk, d_mus[lane], d_ct, d_ss)
+                ctxs[lane].decaps_batch(lp.pid, count, d_sk, d_ct, d_ss2)
+        say("context-stream lanes")
+        for s in streams:
+            s.synchronize()
+        for lane in range(2):
+            ct, ss, ss2 = (x.cpu().numpy() for x in outs[lane])
+            assert np.array_equal(ss, ss2)
+            for i in (0, count - 1):
+                oct_, oss = orc.kem_encaps(op, pk, mus[lane][i].tobytes())
+                assert ct[i].tobytes() == oct_ and ss[i].tobytes() == oss, (lane, i)
+    finally:
+        for c in ctxs:
+            c.close()
