@@ -1234,6 +1234,55 @@ __device__ __forceinline__ void keccak_f1600_dev(uint32_t lo[25], uint32_t hi[25
   }
 }
 
+// SHA3-256 (FIPS 202: rate 136 bytes, domain bits 01, pad10*1) of a message of compile-time
+// length LEN < 136, i.e. one rate block: msg[] is indexed with constants only, so the block,
+// the state and the digest stay in registers.  Returns the digest as eight little-endian words.
+template <int LEN>
+__device__ __forceinline__ void sha3_256_block(const uint8_t (&msg)[LEN], uint32_t d[8]) {
+  static_assert(LEN < 136, "one rate block");
+  uint32_t lo[25], hi[25];
+#pragma unroll
+  for (int w = 0; w < 25; ++w) lo[w] = hi[w] = 0;
+  auto put = [&](int k, uint32_t v) __attribute__((always_inline)) {
+    uint32_t& word = ((k >> 2) & 1) ? hi[k >> 3] : lo[k >> 3];
+    word ^= v << (8 * (k & 3));
+  };
+#pragma unroll
+  for (int k = 0; k < LEN; ++k) put(k, msg[k]);
+  put(LEN, 0x06u);
+  put(135, 0x80u);
+  keccak_f1600_dev(lo, hi);
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    d[2 * w] = lo[w];
+    d[2 * w + 1] = hi[w];
+  }
+}
+
+// coins = H(0x01 || H(pk) || mu)[0:16] and K' = H(H(pk) || mu) for one instance per thread,
+// for a message of MU bytes (each hash is a single rate block).  coins and kprime are the
+// library's own aligned buffers.
+template <int MU>
+__global__ void __launch_bounds__(64) k_fo_coins_t(int count, const uint8_t* __restrict__ pkh,
+                                                   const uint8_t* __restrict__ mu, size_t mu_stride,
+                                                   uint8_t* coins, uint8_t* kprime) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  uint8_t m1[1 + 32 + MU], m2[32 + MU];
+  m1[0] = 1;
+#pragma unroll
+  for (int k = 0; k < 32; ++k) m1[1 + k] = m2[k] = pkh[k];
+  const uint8_t* mi = mu + (size_t)i * mu_stride;
+#pragma unroll
+  for (int k = 0; k < MU; ++k) m1[33 + k] = m2[32 + k] = mi[k];
+  uint32_t d[8];
+  sha3_256_block(m1, d);
+  *(uint4*)(coins + (size_t)i * 16) = make_uint4(d[0], d[1], d[2], d[3]);
+  sha3_256_block(m2, d);
+  *(uint4*)(kprime + (size_t)i * 32) = make_uint4(d[0], d[1], d[2], d[3]);
+  *(uint4*)(kprime + (size_t)i * 32 + 16) = make_uint4(d[4], d[5], d[6], d[7]);
+}
+
 // ---------------------------------------------------------------------------------------
 // Two-lane bit-interleaved Keccak-f[1600].  A pair of adjacent lanes holds one state: lane
 // parity 0 keeps the even bits of every 64-bit lane word, parity 1 the odd bits, each as a
@@ -1433,6 +1482,40 @@ __global__ void k_final_ss(int count, const uint32_t* __restrict__ flags, const 
   for (int k = 0; k < 32; ++k) ss[(size_t)i * 32 + k] = h[k];
 }
 
+// The same with the 64-byte message in registers; kprime and hct are the library's aligned
+// buffers, z and ss may be any byte address (SS_ALIGNED: ss is 4-byte aligned).
+template <bool SS_ALIGNED>
+__global__ void __launch_bounds__(64) k_final_ss_t(int count, const uint32_t* __restrict__ flags,
+                                                   const uint8_t* __restrict__ kprime,
+                                                   const uint8_t* __restrict__ z,
+                                                   const uint8_t* __restrict__ hct, uint8_t* ss) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const uint8_t rej = flags ? (uint8_t)(0u - (uint32_t)(flags[i] != 0)) : 0;
+  uint8_t buf[64];
+  const uint4 k0 = *(const uint4*)(kprime + (size_t)i * 32), k1 = *(const uint4*)(kprime + (size_t)i * 32 + 16);
+  const uint4 h0 = *(const uint4*)(hct + (size_t)i * 32), h1 = *(const uint4*)(hct + (size_t)i * 32 + 16);
+  const uint32_t kw[8] = {k0.x, k0.y, k0.z, k0.w, k1.x, k1.y, k1.z, k1.w};
+  const uint32_t hw[8] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w};
+#pragma unroll
+  for (int k = 0; k < 32; ++k) {
+    const uint8_t zk = z ? z[k] : 0;
+    const uint8_t kk = (uint8_t)(kw[k >> 2] >> (8 * (k & 3)));
+    buf[k] = (uint8_t)((kk & (uint8_t)~rej) | (zk & rej));
+    buf[32 + k] = (uint8_t)(hw[k >> 2] >> (8 * (k & 3)));
+  }
+  uint32_t d[8];
+  sha3_256_block(buf, d);
+  uint8_t* o = ss + (size_t)i * 32;
+  if constexpr (SS_ALIGNED) {
+    *(uint4*)o = make_uint4(d[0], d[1], d[2], d[3]);
+    *(uint4*)(o + 16) = make_uint4(d[4], d[5], d[6], d[7]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 32; ++k) o[k] = (uint8_t)(d[k >> 2] >> (8 * (k & 3)));
+  }
+}
+
 // ======================================================================================
 // Launchers
 // ======================================================================================
@@ -1592,8 +1675,16 @@ hipError_t launch_decrypt(const DecArgs& a, hipStream_t s) {
 hipError_t launch_fo_coins(int count, const uint8_t* pkh, const uint8_t* mu, size_t mu_stride, int mu_bytes,
                            uint8_t* coins, uint8_t* kprime, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fo_coins, dim3(nblk(count, 64)), dim3(64), 0, s, count, pkh, mu, mu_stride, mu_bytes,
-                     coins, kprime);
+  const dim3 g(nblk(count, 64)), b(64);
+  switch (mu_bytes) {  // 8 B bytes for B message bits per coefficient
+#define LWE_FO_CASE(MU_) \
+  case MU_: hipLaunchKernelGGL(k_fo_coins_t<MU_>, g, b, 0, s, count, pkh, mu, mu_stride, coins, kprime); break;
+    LWE_FO_CASE(8) LWE_FO_CASE(16) LWE_FO_CASE(24) LWE_FO_CASE(32) LWE_FO_CASE(40) LWE_FO_CASE(48) LWE_FO_CASE(56)
+    LWE_FO_CASE(64)
+#undef LWE_FO_CASE
+    default:
+      hipLaunchKernelGGL(k_fo_coins, g, b, 0, s, count, pkh, mu, mu_stride, mu_bytes, coins, kprime);
+  }
   return hipGetLastError();
 }
 
@@ -1613,7 +1704,13 @@ hipError_t launch_hash_records(int count, const uint8_t* in, size_t stride, size
 hipError_t launch_final_ss(int count, const uint32_t* flags, const uint8_t* kprime, const uint8_t* z,
                            const uint8_t* hct, uint8_t* ss, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_final_ss, dim3(nblk(count, 64)), dim3(64), 0, s, count, flags, kprime, z, hct, ss);
+  if ((((uintptr_t)kprime | (uintptr_t)hct) & 15) != 0) {  // not the library's own buffers
+    hipLaunchKernelGGL(k_final_ss, dim3(nblk(count, 64)), dim3(64), 0, s, count, flags, kprime, z, hct, ss);
+  } else if ((((uintptr_t)ss) & 15) == 0) {
+    hipLaunchKernelGGL(k_final_ss_t<true>, dim3(nblk(count, 64)), dim3(64), 0, s, count, flags, kprime, z, hct, ss);
+  } else {
+    hipLaunchKernelGGL(k_final_ss_t<false>, dim3(nblk(count, 64)), dim3(64), 0, s, count, flags, kprime, z, hct, ss);
+  }
   return hipGetLastError();
 }
 
