@@ -179,7 +179,7 @@ def main():
     os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, max(1, hwq)))
     if args.gpus != 1:
         print("bench.py measures one GPU: the KEM hot path here runs on a single MI355X; "
-              "--gpus %d is not supported (every GPU box has one GPU)" % args.gpus, file=sys.stderr)
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         return 2
     if args.large:
         return large(args)

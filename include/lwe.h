@@ -56,7 +56,7 @@ typedef enum {
   LWE_EINVAL = -1,       /* bad argument: unknown parameter id, NULL pointer, bad size */
   LWE_ENOMEM = -2,       /* device allocation failed or would exceed the context budget */
   LWE_EDEVICE = -3,      /* a HIP runtime call failed */
-  LWE_EUNSUPPORTED = -4  /* valid request that this build does not implement */
+  LWE_EUNSUPPORTED = -4  /* valid request that the library does not implement */
 } lwe_status;
 
 /* Parameter set description (Table 1 of the paper gives the prime-q sets it evaluated;

@@ -717,7 +717,8 @@ __global__ void __launch_bounds__(1024) k_prod_stream(ProdArgs a, int ks_per_wav
 // transposed tile (A strip as the first operand), so each lane ends up holding four
 // consecutive columns of one output row: the epilogue reads E' four bytes and writes the
 // result eight bytes at a time.
-//   LDS: [ksteps][CG][limb][64 lanes][16 bytes] after the 4 KB of AES tables.
+//   LDS: the strip, [ksteps][CG][limb][64 lanes][16 bytes] (dynamic), beside the AES tables
+//   (static: 32 KB conflict-free or 4 KB, see TAB below).
 // Workgroup ids are remapped so that each XCD (ids congruent mod 8) processes a
 // contiguous range of tiles, i.e. the same row chunks share that XCD's L2.
 // ======================================================================================

@@ -9,7 +9,7 @@ if ROOT not in sys.path:
 
 
 def pytest_configure(config):
-    config.addinivalue_line("markers", "gpu: needs a HIP device (MI355X); run on the GPU box")
+    config.addinivalue_line("markers", "gpu: needs a HIP device (MI355X)")
     config.addinivalue_line("markers", "slow: long CPU-only check, skipped unless LWE_SLOW=1")
 
 
