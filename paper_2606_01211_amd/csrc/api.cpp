@@ -261,11 +261,14 @@ bool use_host_hash(lwe_ctx* c, int pid, size_t count) {
 // ------------------------------------------------------------------------------------
 // Product launch planning
 // ------------------------------------------------------------------------------------
+// The strip product (large row counts) reads S' in fragment order; the streaming one row-major.
+bool uses_strip(int M, bool trans, bool per_inst_A) { return !trans && !per_inst_A && M >= 256; }
+
 int run_product(lwe_ctx* c, int pid, const Params& p, ProdArgs a, bool trans, hipStream_t s) {
   // a: operands, epilogue fields, M and ncols are filled in by the caller
   const int ksteps = (p.n + 63) / 64;
   const lwe_tuning& tu = tuning_of(c, pid);
-  const bool strip = !trans && !a.per_inst_A && a.M >= 256;
+  const bool strip = uses_strip(a.M, trans, a.per_inst_A != 0);
   // Unfused variant: expand A once into device memory and let the product read it (one A per
   // call, so not for key-generation batches, where every instance has its own A).
   if (tu.a_source == 1 && (!a.per_inst_A || a.M == 8)) {
@@ -348,7 +351,9 @@ int encrypt_core(lwe_ctx* c, int pid, const Params& p, size_t count, const uint8
   const int n = p.n;
   int8_t *X, *E, *E2;
   uint32_t* rkA;
-  LWE_CHECK(ensure_t(c, B_X, count * 8 * (size_t)p.ldx, &X));
+  const bool frag = uses_strip((int)(count * 8), false, false);
+  // fragment order covers whole 16-row groups
+  LWE_CHECK(ensure_t(c, B_X, (count * 8 + 15) / 16 * 16 * (size_t)p.ldx, &X));
   LWE_CHECK(ensure_t(c, B_E, count * 8 * (size_t)n, &E));
   LWE_CHECK(ensure_t(c, B_E2, count * 64, &E2));
   LWE_CHECK(ensure_t(c, B_RKA, 44 * 4, &rkA));
@@ -363,6 +368,7 @@ int encrypt_core(lwe_ctx* c, int pid, const Params& p, size_t count, const uint8
   sa.nseg = 3;
   for (int k = 0; k < MAX_K; ++k) sa.T2[k] = (uint32_t)p.T[k] * 0x10001u;
   sa.X = X;
+  sa.x_frag = frag ? 1 : 0;
   sa.E = E;
   sa.E2 = E2;
   KLAUNCH("sample", s, launch_sample(sa, (int)count, s));

@@ -423,8 +423,10 @@ __global__ void __launch_bounds__(64 * SAMPLE_WAVES) k_sample(SampleArgs a, int 
     for (int i = 0; i < 36; ++i) rkr[i] = rotl32(rk[4 + i], 24);
     if (chunk == 0 && a.ldx > n) {  // zero the padding columns of segment 0
       const int pad = a.ldx - n;
-      for (int idx = lane; idx < 8 * pad; idx += 64)
-        a.X[((size_t)inst * 8 + idx / pad) * a.ldx + n + idx % pad] = 0;
+      for (int idx = lane; idx < 8 * pad; idx += 64) {
+        const int row = inst * 8 + idx / pad, k = n + idx % pad;
+        a.X[a.x_frag ? frag_offset(row, k, a.ldx >> 6) : (size_t)row * a.ldx + k] = 0;
+      }
     }
     uint32_t o[SAMPLE_ILP][4];
     int tt[SAMPLE_ILP];
@@ -451,7 +453,10 @@ __global__ void __launch_bounds__(64 * SAMPLE_WAVES) k_sample(SampleArgs a, int 
       const int w0 = 8 * lb;
       if (seg == 0) {
         const int row = w0 / n, col = w0 - row * n;
-        *(uint2*)(a.X + ((size_t)inst * 8 + row) * a.ldx + col) = make_uint2(p0, p1);
+        // eight consecutive columns (col is a multiple of 8) stay inside one 16-byte slot
+        const int grow = inst * 8 + row;
+        *(uint2*)(a.X + (a.x_frag ? frag_offset(grow, col, a.ldx >> 6) : (size_t)grow * a.ldx + col)) =
+            make_uint2(p0, p1);
         if (a.X16)
           *(uint4*)(a.X16 + (size_t)inst * a.x16_stride + 2 * ((size_t)row * n + col)) =
               make_uint4(h[0], h[1], h[2], h[3]);
@@ -841,7 +846,8 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
   // multiple of three steps), so no register moves tie a wait on a fresh load to the current
   // step.  Rows past the chunk end read row m_begin instead (their results are never
   // stored), and X loads past the last real step re-read it (they meet zero strip rows), so
-  // every operand load is unconditional and in bounds.
+  // every operand load is unconditional and in bounds.  S' is in fragment order
+  // (frag_offset): a wave's fragment of one 16-row group and step is 1 KB contiguous.
   const int m_begin = mt * a.m_tile, m_end = min(a.M, m_begin + a.m_tile);
   const int rows = m_end - m_begin;
   const int nrb = (rows + 16 * RG - 1) / (16 * RG);
@@ -851,12 +857,13 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
   // so the epilogue is E' add, mask and one 8-byte store (or compare) per tile.  The other
   // workgroups (the strip holding V's columns, split-K) take the general epilogue.
   const bool fast = a.n_kc == 1 && nn0 + 16 * CG <= n;
+  const int xsteps = a.ldx >> 6;
   auto row_ptrs = [&](int rb, const int8_t* (&p)[RG]) __attribute__((always_inline)) {
     const int rbase = m_begin + rb * 16 * RG;
 #pragma unroll
     for (int rg = 0; rg < RG; ++rg) {
-      const int row = rbase + rg * 16 + (lane & 15);
-      p[rg] = a.X + (size_t)(row < m_end ? row : m_begin) * a.ldx + k0 + 16 * (lane >> 4);
+      const int g0 = rbase + rg * 16;  // groups past the chunk end read the chunk's first one
+      p[rg] = a.X + ((size_t)((g0 < m_end ? g0 : m_begin) >> 4) * xsteps + (k0 >> 6)) * 1024 + 16 * lane;
     }
   };
   const int8_t* xp[RG];  // current row block
@@ -868,7 +875,7 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
   v4i yb[YD][2];    // strip fragment ring: slot = phase mod YD, a phase being one (step, cg)
   auto load_xs = [&](v4i (&dst)[RG], const int8_t* const (&p)[RG], int s) __attribute__((always_inline)) {
 #pragma unroll
-    for (int rg = 0; rg < RG; ++rg) dst[rg] = *(const v4i*)(p[rg] + 64 * s);
+    for (int rg = 0; rg < RG; ++rg) dst[rg] = *(const v4i*)(p[rg] + 1024 * (size_t)s);
   };
   auto load_y = [&](v4i (&dst)[2], int s, int cg) __attribute__((always_inline)) {
     dst[0] = *(const v4i*)(strip + ((size_t)((s * CG + cg) * 2) * 64 + lane) * 16);

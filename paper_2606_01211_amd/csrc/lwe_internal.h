@@ -23,10 +23,19 @@ enum ProdMode : int { PM_KEYGEN = 0, PM_ENCRYPT = 1, PM_COMPARE = 2 };
 // (S^T stacks for keygen, S' stacks for encryption) and Y is A (encryption) or A^T
 // (keygen) regenerated from AES-128-CTR, extended for encryption by the 8 columns of
 // B = (B^T)^T so that V = S' B is computed by the same contraction.
+// Byte offset of S' element (row, k) in MFMA fragment order, the layout the strip product
+// reads: 16-row groups, then 64-column contraction steps, then the 64 lanes of the operand
+// fragment (lane = row % 16 + 16 * (k % 64 / 16)), 16 bytes each.  steps = ldx / 64.
+LWE_HD size_t frag_offset(int row, int k, int steps) {
+  const int lane = (row & 15) | (((k & 63) >> 4) << 4);
+  return (((size_t)(row >> 4) * steps + (k >> 6)) * 64 + lane) * 16 + (k & 15);
+}
+
 struct ProdArgs {
   const uint32_t* rkA;   // round keys of seedA: 44 words, or [inst][44] if per_inst_A
   const uint32_t* T0;    // AES T-table (256 words, global)
-  const int8_t* X;       // [M][ldx] int8, zero padded beyond n
+  const int8_t* X;       // [M][ldx] int8, zero padded beyond n; the strip product reads it in
+                         // fragment order (frag_offset), rows rounded up to 16
   int ldx;
   int M;                 // valid rows (8 per instance)
   int n, logq, B;
@@ -61,7 +70,9 @@ struct SampleArgs {
   int n, K, ldx;
   int nseg;              // 2 (keygen: S^T, E^T) or 3 (encryption: S', E', E'')
   uint32_t T2[MAX_K];    // CDF entries T[0..K-1], each replicated in both 16-bit halves
-  int8_t* X;             // segment 0 (domain 1): [count*8][ldx]
+  int8_t* X;             // segment 0 (domain 1): [count*8][ldx] row-major, or in MFMA fragment
+                         // order when x_frag is set (see frag_offset)
+  int x_frag;
   uint8_t* X16;          // optional int16 copy of segment 0 (secret key bytes), may be null
   size_t x16_stride;
   int8_t* E;             // segment 1 (domain 2): [count*8][n]
