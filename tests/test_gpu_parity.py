@@ -430,3 +430,22 @@ def test_context_stream_lanes(orc):
     finally:
         for c in ctxs:
             c.close()
+
+
+def test_strip_split_k_8192(ctx, orc):
+    """A batch of 32 encryptions at n = 8192: the strip product with its contraction split in
+    two K chunks (S' in fragment order, partial sums accumulated and finished by k_finalize),
+    against the oracle at both ends of the batch."""
+    lp, op = _pair(orc, 8192)
+    g = lwe_inputs.rng(0, 8192 + 32)
+    pk, _ = _keypair(orc, op, g)
+    count = 32
+    coins = lwe_inputs.coins(g, count)
+    mus = lwe_inputs.messages(g, count, op.mu_bytes)
+    ct = np.zeros((count, op.ct_bytes), np.uint8)
+    say("strip split-K 8192", count)
+    ctx.test_encrypt(lp.pid, count, pk, coins, mus, ct)
+    Bt = np.frombuffer(pk[16:], "<u2").reshape(8, 8192)
+    for i in (0, count - 1):
+        Bp, V = orc.pke_encrypt(op, pk[:16], Bt, coins[i].tobytes(), mus[i].tobytes())
+        assert ct[i].tobytes() == Bp.astype("<u2").tobytes() + V.astype("<u2").tobytes(), i
