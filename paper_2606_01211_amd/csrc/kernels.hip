@@ -1160,23 +1160,8 @@ __global__ void __launch_bounds__(256) k_decrypt(DecArgs a) {
 }
 
 // ======================================================================================
-// SHA3-256 sponges (one message per thread).
+// SHA3-256 sponges.
 // ======================================================================================
-// coins = H(0x01 || pkh || mu)[0:16], K' = H(pkh || mu)
-__global__ void k_fo_coins(int count, const uint8_t* __restrict__ pkh, const uint8_t* __restrict__ mu,
-                           size_t mu_stride, int mu_bytes, uint8_t* coins, uint8_t* kprime) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
-  uint8_t h[32], pk[32], m[64];
-  const uint8_t one = 1;
-  for (int k = 0; k < 32; ++k) pk[k] = pkh[k];
-  for (int k = 0; k < mu_bytes; ++k) m[k] = mu[(size_t)i * mu_stride + k];
-  sha3_256_3(&one, 1, pk, 32, m, mu_bytes, h);
-  for (int k = 0; k < 16; ++k) coins[(size_t)i * 16 + k] = h[k];
-  sha3_256_3(pk, 32, m, mu_bytes, nullptr, 0, h);
-  for (int k = 0; k < 32; ++k) kprime[(size_t)i * 32 + k] = h[k];
-}
-
 // Keccak-f[1600] on 32-bit halves: lane (x, y) is (hi[x + 5y], lo[x + 5y]).  Written with the
 // gfx950 three-input bit operations: a 3-way XOR (LUT 0x96) and chi's a ^ (~b & c) (LUT 0xD2),
 // and 64-bit rotations as two funnel shifts (v_alignbit).
@@ -1474,24 +1459,9 @@ k_hash_records(int count, const uint8_t* __restrict__ in, size_t stride, size_t 
   }
 }
 
-// ss = H(pre || H(ct)) with pre = K' (accepted) or z (rejected), selected without branches.
-__global__ void k_final_ss(int count, const uint32_t* __restrict__ flags, const uint8_t* __restrict__ kprime,
-                           const uint8_t* __restrict__ z, const uint8_t* __restrict__ hct, uint8_t* ss) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
-  const uint8_t rej = flags ? (uint8_t)(0u - (uint32_t)(flags[i] != 0)) : 0;
-  uint8_t buf[64], h[32];
-  for (int k = 0; k < 32; ++k) {
-    const uint8_t zk = z ? z[k] : 0;
-    buf[k] = (uint8_t)((kprime[(size_t)i * 32 + k] & (uint8_t)~rej) | (zk & rej));
-    buf[32 + k] = hct[(size_t)i * 32 + k];
-  }
-  sha3_256(buf, 64, h);
-  for (int k = 0; k < 32; ++k) ss[(size_t)i * 32 + k] = h[k];
-}
-
-// The same with the 64-byte message in registers; kprime and hct are the library's aligned
-// buffers, z and ss may be any byte address (SS_ALIGNED: ss is 4-byte aligned).
+// ss = H(pre || H(ct)) with pre = K' (accepted) or z (rejected), selected without branches; the
+// 64-byte message is one rate block kept in registers.  kprime and hct are the library's
+// 16-byte aligned buffers; z and ss may be any byte address (SS_ALIGNED: ss is 16-byte aligned).
 template <bool SS_ALIGNED>
 __global__ void __launch_bounds__(64) k_final_ss_t(int count, const uint32_t* __restrict__ flags,
                                                    const uint8_t* __restrict__ kprime,
@@ -1690,8 +1660,8 @@ hipError_t launch_fo_coins(int count, const uint8_t* pkh, const uint8_t* mu, siz
     LWE_FO_CASE(8) LWE_FO_CASE(16) LWE_FO_CASE(24) LWE_FO_CASE(32) LWE_FO_CASE(40) LWE_FO_CASE(48) LWE_FO_CASE(56)
     LWE_FO_CASE(64)
 #undef LWE_FO_CASE
-    default:
-      hipLaunchKernelGGL(k_fo_coins, g, b, 0, s, count, pkh, mu, mu_stride, mu_bytes, coins, kprime);
+    default:  // the registry allows 1 to 8 message bits per coefficient
+      return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
@@ -1712,9 +1682,8 @@ hipError_t launch_hash_records(int count, const uint8_t* in, size_t stride, size
 hipError_t launch_final_ss(int count, const uint32_t* flags, const uint8_t* kprime, const uint8_t* z,
                            const uint8_t* hct, uint8_t* ss, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  if ((((uintptr_t)kprime | (uintptr_t)hct) & 15) != 0) {  // not the library's own buffers
-    hipLaunchKernelGGL(k_final_ss, dim3(nblk(count, 64)), dim3(64), 0, s, count, flags, kprime, z, hct, ss);
-  } else if ((((uintptr_t)ss) & 15) == 0) {
+  if ((((uintptr_t)kprime | (uintptr_t)hct) & 15) != 0) return hipErrorInvalidValue;  // own buffers only
+  if ((((uintptr_t)ss) & 15) == 0) {
     hipLaunchKernelGGL(k_final_ss_t<true>, dim3(nblk(count, 64)), dim3(64), 0, s, count, flags, kprime, z, hct, ss);
   } else {
     hipLaunchKernelGGL(k_final_ss_t<false>, dim3(nblk(count, 64)), dim3(64), 0, s, count, flags, kprime, z, hct, ss);
