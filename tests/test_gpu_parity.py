@@ -449,3 +449,32 @@ def test_strip_split_k_8192(ctx, orc):
     for i in (0, count - 1):
         Bp, V = orc.pke_encrypt(op, pk[:16], Bt, coins[i].tobytes(), mus[i].tobytes())
         assert ct[i].tobytes() == Bp.astype("<u2").tobytes() + V.astype("<u2").tobytes(), i
+
+
+def test_strip_small_tables_4096(ctx, orc):
+    """40 encapsulations at n = 4096 (a key size of the serving mix): the strip there is too
+    tall for the 32 KB conflict-free AES tables beside it, so the strip kernel regenerates A
+    with the 4 KB tables.  Encryption and the decapsulation's compare mode against the oracle,
+    one ciphertext tampered."""
+    lp, op = _pair(orc, 4096)
+    g = lwe_inputs.rng(0, 4096 + 40)
+    pk, sk = _keypair(orc, op, g)
+    count = 40
+    mus = lwe_inputs.messages(g, count, op.mu_bytes)
+    ct = np.zeros((count, op.ct_bytes), np.uint8)
+    ss = np.zeros((count, 32), np.uint8)
+    say("strip 4 KB tables 4096 encaps", count)
+    ctx.encaps_batch(lp.pid, count, pk, mus, ct, ss)
+    for i in (0, count - 1):
+        oct_, oss = orc.kem_encaps(op, pk, mus[i].tobytes())
+        assert ct[i].tobytes() == oct_ and ss[i].tobytes() == oss, i
+    bad = ct.copy()
+    bad[7, 16 * 4096 + 5] ^= 0x10  # a V coefficient of instance 7
+    ss2 = np.zeros((count, 32), np.uint8)
+    say("strip 4 KB tables 4096 decaps", count)
+    ctx.decaps_batch(lp.pid, count, sk, bad, ss2)
+    for i in range(count):
+        if i != 7:
+            assert ss2[i].tobytes() == ss[i].tobytes(), i
+    oss, ok = orc.kem_decaps(op, sk, bad[7].tobytes())
+    assert not ok and ss2[7].tobytes() == oss
