@@ -145,6 +145,28 @@ int stage_in(lwe_ctx* c, BufId id, const void* src, size_t bytes, hipStream_t s,
   return LWE_OK;
 }
 
+// Host copies of two caller buffers (either may be on the device) with a single wait.
+int host_copy2(const void* a, size_t na, std::vector<uint8_t>& oa, const void* b, size_t nb,
+               std::vector<uint8_t>& ob, hipStream_t s) {
+  oa.resize(na);
+  ob.resize(nb);
+  bool wait = false;
+  if (is_device_ptr(a)) {
+    HIP_CHECK(hipMemcpyAsync(oa.data(), a, na, hipMemcpyDeviceToHost, s));
+    wait = true;
+  } else {
+    memcpy(oa.data(), a, na);
+  }
+  if (is_device_ptr(b)) {
+    HIP_CHECK(hipMemcpyAsync(ob.data(), b, nb, hipMemcpyDeviceToHost, s));
+    wait = true;
+  } else {
+    memcpy(ob.data(), b, nb);
+  }
+  if (wait) HIP_CHECK(hipStreamSynchronize(s));
+  return LWE_OK;
+}
+
 // Host copy of a caller buffer (which may be on the device); synchronises when copying.
 int host_copy(const void* src, size_t bytes, hipStream_t s, std::vector<uint8_t>& out) {
   out.resize(bytes);
@@ -684,9 +706,14 @@ int lwe_encaps_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* pk, const
   DevGuard g(c->device);
   hipStream_t s = pick_stream(c, stream);
   const size_t mb = p.mu_bytes;
-  // H(pk) on the host (cached per public key)
-  std::vector<uint8_t> hpk;
-  LWE_CHECK(host_copy(pk, p.pk_bytes, s, hpk));
+  // H(pk) on the host (cached per public key); with host hashing the messages come back in the
+  // same wait
+  const bool hh = use_host_hash(c, pid, count);
+  std::vector<uint8_t> hpk, hmu;
+  if (hh)
+    LWE_CHECK(host_copy2(pk, p.pk_bytes, hpk, mu, count * mb, hmu, s));
+  else
+    LWE_CHECK(host_copy(pk, p.pk_bytes, s, hpk));
   uint8_t pkh[32];
   host_pkh(c, hpk.data(), p.pk_bytes, pkh);
   const uint8_t *dpk, *dmu;
@@ -700,10 +727,8 @@ int lwe_encaps_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* pk, const
   LWE_CHECK(ensure_t(c, B_COINS, count * 16, &dcoins));
   LWE_CHECK(ensure_t(c, B_KP, count * 32, &dkp));
   LWE_CHECK(ensure_t(c, B_RK, count * 44 * 4, &drk));
-  const bool hh = use_host_hash(c, pid, count);
-  std::vector<uint8_t> hmu, hcoins, hkp;
+  std::vector<uint8_t> hcoins, hkp;
   if (hh) {
-    LWE_CHECK(host_copy(mu, count * mb, s, hmu));
     hcoins.resize(count * 16);
     hkp.resize(count * 32);
     const uint8_t one = 1;
@@ -799,11 +824,18 @@ int lwe_decaps_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* sk, const
   const bool hh = use_host_hash(c, pid, count);
   std::vector<uint8_t> hsk_tail, hkp, hct, hhct;
   if (hh) {
-    // pkh and z from the secret key, mu' to the host, coins' and K'' on the host
+    // pkh and z from the secret key, mu' to the host, coins' and K'' on the host.  The received
+    // ciphertexts come back in the same wait, so that their hashing on the host overlaps the
+    // re-encryption below.
     std::vector<uint8_t> hmu(count * mb), hcoins(count * 16);
     hsk_tail.resize(64);
     HIP_CHECK(hipMemcpyAsync(hsk_tail.data(), dsk + off_pkh, 64, hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipMemcpyAsync(hmu.data(), dmu2, hmu.size(), hipMemcpyDeviceToHost, s));
+    hct.resize(count * p.ct_bytes);
+    if (is_device_ptr(ct))
+      HIP_CHECK(hipMemcpyAsync(hct.data(), ct, hct.size(), hipMemcpyDeviceToHost, s));
+    else
+      memcpy(hct.data(), ct, hct.size());
     HIP_CHECK(hipStreamSynchronize(s));
     hkp.resize(count * 32);
     const uint8_t one = 1;
@@ -821,7 +853,6 @@ int lwe_decaps_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* sk, const
     std::vector<uint32_t> hflags(count);
     HIP_CHECK(hipMemcpyAsync(hflags.data(), dflags, count * 4, hipMemcpyDeviceToHost, s));
     // H(ct) on the host while the device re-encrypts
-    LWE_CHECK(host_copy(ct, count * p.ct_bytes, s, hct));
     hhct.resize(count * 32);
     host_for(c->host_threads, count,
              [&](size_t i) { sha3_256(hct.data() + i * p.ct_bytes, p.ct_bytes, hhct.data() + i * 32); });
