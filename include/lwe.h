@@ -152,7 +152,8 @@ int lwe_test_sha3(lwe_ctx* ctx, size_t count, size_t len, const uint8_t* in, uin
 
 /* Kernel timing for measurement.  While enabled, every kernel the context launches is
  * bracketed by a pair of HIP events on the stream it runs on.  lwe_prof_read synchronises
- * the recorded events and returns, for one kernel name ("sample", "prod_strip",
+ * the recorded events and returns, for one kernel name ("sample", "prod_strip" (encryption),
+ * "prod_strip_cmp" (the re-encryption and compare of a decapsulation),
  * "prod_stream", "finalize", "decrypt", "fo_coins", "expand_keys", "hash_records",
  * "final_ss", "fill", "keystream", "sample_stream", "expand_A"), the number of launches and their
  * summed device time since the last reset. */

@@ -355,7 +355,9 @@ int run_product(lwe_ctx* c, int pid, const Params& p, ProdArgs a, bool trans, hi
       LWE_CHECK(ensure_t(c, B_ACC, (size_t)a.M * a.acc_ld * 4, &a.acc32));
       KLAUNCH("fill", s, launch_fill_u32((uint32_t*)a.acc32, (size_t)a.M * a.acc_ld, 0, s));
     }
-    KLAUNCH("prod_strip", s, launch_product_strip(a, CG, RG, unr, s));
+    // timed under separate names: the compare launch of a decapsulation shares the GPU with its
+    // concurrent hash
+    KLAUNCH(a.mode == PM_COMPARE ? "prod_strip_cmp" : "prod_strip", s, launch_product_strip(a, CG, RG, unr, s));
   }
   if (a.n_kc > 1) KLAUNCH("finalize", s, launch_finalize(a, s));
   return LWE_OK;

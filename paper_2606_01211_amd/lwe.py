@@ -33,7 +33,7 @@ EXPORTS = [
     "lwe_prof_enable", "lwe_prof_reset", "lwe_prof_read",
 ]
 
-KERNELS = ["sample", "prod_strip", "prod_stream", "finalize", "decrypt", "fo_coins", "expand_keys",
+KERNELS = ["sample", "prod_strip", "prod_strip_cmp", "prod_stream", "finalize", "decrypt", "fo_coins", "expand_keys",
            "hash_records", "final_ss", "fill", "keystream", "sample_stream", "expand_A"]
 
 
