@@ -2,7 +2,8 @@
 //
 //  * AES-128-CTR with T-tables in LDS: the seed expansion sample(rho) of Alg. 1 that yields
 //    the public matrix A, and the device-side noise source of Sec. 3.3.  A is regenerated
-//    tile by tile inside the products (Sec. 3.5) and never written to HBM.
+//    tile by tile inside the products (Sec. 3.5) and never written to HBM (an unfused
+//    variant, kept for comparison, expands it once per call and reads it back).
 //  * CDF-table sampling of the secrets and errors (Alg. 1-2).
 //  * The mod-2^16 products B^T = S^T A^T + E^T, B' = S' A + E', V = S' B + E'' + enc(mu)
 //    (Alg. 1-2) and M = V - B' S (Alg. 3) on int8 MFMA: each 16-bit operand is split into two
