@@ -186,6 +186,62 @@ __device__ __forceinline__ void aes_ctr_block_rep(const uint32_t* __restrict__ T
   }
 }
 
+// Counter blocks whose domain word and high counter word (zero: block indices below 2^32) are
+// the same for a whole wave differ only in state word 3 after the initial round-key XOR, so 12
+// of round 1's 16 lookups are the same for every block.  aes_round1_fixed_rep computes them once
+// (per wave and key), folded the way each column needs them:
+//   column 0: fx[0] ^ rotl8(fx[1] ^ T2[s3.b3]),  column 1: fx[2] ^ T2[s3.b2],
+//   column 2: fx[3] ^ rotl8(fx[4] ^ T0[s3.b1]),  column 3: fx[5] ^ T0[s3.b0];
+// aes_ctr_block_rep_fixed then runs one block from them (same result as aes_ctr_block_rep).
+template <class RK>
+__device__ __forceinline__ void aes_round1_fixed_rep(const uint32_t* __restrict__ TR, uint32_t off0, uint32_t off2,
+                                                     const RK& rk, const uint32_t* rkr, uint32_t dom_le,
+                                                     uint32_t fx[6]) {
+  const uint32_t s0 = dom_le ^ rk[0], s1 = rk[1], s2 = rk[2];
+  fx[0] = rep_look<0>(TR, s0, off0) ^ rep_look<2>(TR, s2, off2);
+  fx[1] = rep_look<1>(TR, s1, off0) ^ rkr[0];
+  fx[2] = rep_look<0>(TR, s1, off0) ^ rotl32(x3(rep_look<1>(TR, s2, off0), rep_look<3>(TR, s0, off2), rkr[1]), 8);
+  fx[3] = rep_look<0>(TR, s2, off0) ^ rep_look<2>(TR, s0, off2);
+  fx[4] = rep_look<3>(TR, s1, off2) ^ rkr[2];
+  fx[5] = rep_look<2>(TR, s1, off2) ^ rotl32(x3(rep_look<1>(TR, s0, off0), rep_look<3>(TR, s2, off2), rkr[3]), 8);
+}
+
+template <class RK>
+__device__ __forceinline__ void aes_ctr_block_rep_fixed(const uint32_t* __restrict__ TR, uint32_t off0,
+                                                        uint32_t off2, const RK& rk, const uint32_t* rkr,
+                                                        const uint32_t fx[6], uint32_t b_lo, uint32_t o[4]) {
+  const uint32_t s3 = bswap32(b_lo) ^ rk[3];
+  uint32_t s[4];
+  s[0] = fx[0] ^ rotl32(fx[1] ^ rep_look<3>(TR, s3, off2), 8);
+  s[1] = fx[2] ^ rep_look<2>(TR, s3, off2);
+  s[2] = fx[3] ^ rotl32(fx[4] ^ rep_look<1>(TR, s3, off0), 8);
+  s[3] = fx[5] ^ rep_look<0>(TR, s3, off0);
+#pragma unroll
+  for (int r = 2; r < 10; ++r) {
+    uint32_t t[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t a0 = rep_look<0>(TR, s[j], off0);
+      const uint32_t a1 = rep_look<1>(TR, s[(j + 1) & 3], off0);
+      const uint32_t a2 = rep_look<2>(TR, s[(j + 2) & 3], off2);
+      const uint32_t a3 = rep_look<3>(TR, s[(j + 3) & 3], off2);
+      t[j] = x3(a0, a2, rotl32(x3(a1, a3, rkr[4 * (r - 1) + j]), 8));
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s[j] = t[j];
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t a0 = rep_look<0>(TR, s[j], off0);
+    const uint32_t a1 = rep_look<1>(TR, s[(j + 1) & 3], off0);
+    const uint32_t a2 = rep_look<2>(TR, s[(j + 2) & 3], off0);
+    const uint32_t a3 = rep_look<3>(TR, s[(j + 3) & 3], off0);
+    const uint32_t lo = __builtin_amdgcn_perm(a1, a0, 0x0c0c0602u);
+    const uint32_t hi = __builtin_amdgcn_perm(a3, a2, 0x06020c0cu);
+    o[j] = x3(lo, hi, rk[40 + j]);
+  }
+}
+
 // ======================================================================================
 // AES with 32 lane-indexed copies of T0 only (32 KB, conflict-free lookups), for kernels that
 // cannot spare the 64 KB of the T0/T2 copies above: word e*32 + c holds T0[e] for copy
@@ -229,6 +285,55 @@ __device__ __forceinline__ void aes_ctr_block_q(const uint32_t* __restrict__ TQ,
     for (int j = 0; j < 4; ++j) s[j] = t[j];
   }
   // Final round: S(x) is byte 2 of T0[x].
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t a0 = q_look<0>(TQ, s[j], off);
+    const uint32_t a1 = q_look<1>(TQ, s[(j + 1) & 3], off);
+    const uint32_t a2 = q_look<2>(TQ, s[(j + 2) & 3], off);
+    const uint32_t a3 = q_look<3>(TQ, s[(j + 3) & 3], off);
+    const uint32_t lo = __builtin_amdgcn_perm(a1, a0, 0x0c0c0602u);
+    const uint32_t hi = __builtin_amdgcn_perm(a3, a2, 0x06020c0cu);
+    o[j] = x3(lo, hi, rk[40 + j]);
+  }
+}
+
+// The fixed-round-1 form (see aes_round1_fixed_rep) for the T0-only tables.
+template <class RK>
+__device__ __forceinline__ void aes_round1_fixed_q(const uint32_t* __restrict__ TQ, uint32_t off, const RK& rk,
+                                                   const uint32_t* rkr, uint32_t dom_le, uint32_t fx[6]) {
+  const uint32_t s0 = dom_le ^ rk[0], s1 = rk[1], s2 = rk[2];
+  fx[0] = q_look<0>(TQ, s0, off) ^ rotl32(q_look<2>(TQ, s2, off), 16);
+  fx[1] = q_look<1>(TQ, s1, off) ^ rkr[0];
+  fx[2] = q_look<0>(TQ, s1, off) ^ rotl32(x3(q_look<1>(TQ, s2, off), rotl32(q_look<3>(TQ, s0, off), 16), rkr[1]), 8);
+  fx[3] = q_look<0>(TQ, s2, off) ^ rotl32(q_look<2>(TQ, s0, off), 16);
+  fx[4] = rotl32(q_look<3>(TQ, s1, off), 16) ^ rkr[2];
+  fx[5] = rotl32(q_look<2>(TQ, s1, off), 16) ^ rotl32(x3(q_look<1>(TQ, s0, off), rotl32(q_look<3>(TQ, s2, off), 16), rkr[3]), 8);
+}
+
+template <class RK>
+__device__ __forceinline__ void aes_ctr_block_q_fixed(const uint32_t* __restrict__ TQ, uint32_t off, const RK& rk,
+                                                      const uint32_t* rkr, const uint32_t fx[6], uint32_t b_lo,
+                                                      uint32_t o[4]) {
+  const uint32_t s3 = bswap32(b_lo) ^ rk[3];
+  uint32_t s[4];
+  s[0] = fx[0] ^ rotl32(fx[1] ^ rotl32(q_look<3>(TQ, s3, off), 16), 8);
+  s[1] = fx[2] ^ rotl32(q_look<2>(TQ, s3, off), 16);
+  s[2] = fx[3] ^ rotl32(fx[4] ^ q_look<1>(TQ, s3, off), 8);
+  s[3] = fx[5] ^ q_look<0>(TQ, s3, off);
+#pragma unroll
+  for (int r = 2; r < 10; ++r) {
+    uint32_t t[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t a0 = q_look<0>(TQ, s[j], off);
+      const uint32_t a1 = q_look<1>(TQ, s[(j + 1) & 3], off);
+      const uint32_t a2 = q_look<2>(TQ, s[(j + 2) & 3], off);
+      const uint32_t a3 = q_look<3>(TQ, s[(j + 3) & 3], off);
+      t[j] = x3(a0, rotl32(a2, 16), rotl32(x3(a1, rotl32(a3, 16), rkr[4 * (r - 1) + j]), 8));
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s[j] = t[j];
+  }
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const uint32_t a0 = q_look<0>(TQ, s[j], off);
@@ -431,14 +536,31 @@ __global__ void __launch_bounds__(64 * SAMPLE_WAVES) k_sample(SampleArgs a, int 
     }
     uint32_t o[SAMPLE_ILP][4];
     int tt[SAMPLE_ILP];
+    // A unit inside one segment (the usual case) has a wave-uniform domain word: round 1's
+    // fixed lookups are done once for its blocks.
+    const int t_first = chunk * per_unit, t_last = min(t_first + per_unit - 1, total - 1);
+    const int seg_first = t_first < n ? 0 : (t_first < 2 * n ? 1 : 2);
+    const int seg_last = t_last < n ? 0 : (t_last < 2 * n ? 1 : 2);
+    if (seg_first == seg_last) {
+      uint32_t fx[6];
+      aes_round1_fixed_rep(TR, off0, off2, rk, rkr, bswap32((uint32_t)(seg_first + 1)), fx);
 #pragma unroll
-    for (int j = 0; j < SAMPLE_ILP; ++j) {
-      const int t = chunk * per_unit + j * 64 + lane;
-      tt[j] = t;
-      const int tc = t < total ? t : total - 1;
-      const int seg = tc < n ? 0 : (tc < 2 * n ? 1 : 2);
-      const int lb = tc - seg * n;
-      aes_ctr_block_rep(TR, off0, off2, rk, rkr, bswap32((uint32_t)(seg + 1)), (uint64_t)lb, o[j]);
+      for (int j = 0; j < SAMPLE_ILP; ++j) {
+        const int t = t_first + j * 64 + lane;
+        tt[j] = t;
+        const int tc = t < total ? t : total - 1;
+        aes_ctr_block_rep_fixed(TR, off0, off2, rk, rkr, fx, (uint32_t)(tc - seg_first * n), o[j]);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < SAMPLE_ILP; ++j) {
+        const int t = t_first + j * 64 + lane;
+        tt[j] = t;
+        const int tc = t < total ? t : total - 1;
+        const int seg = tc < n ? 0 : (tc < 2 * n ? 1 : 2);
+        const int lb = tc - seg * n;
+        aes_ctr_block_rep(TR, off0, off2, rk, rkr, bswap32((uint32_t)(seg + 1)), (uint64_t)lb, o[j]);
+      }
     }
 #pragma unroll
     for (int j = 0; j < SAMPLE_ILP; ++j) {
@@ -558,6 +680,9 @@ __global__ void __launch_bounds__(1024) k_prod_stream(ProdArgs a, int ks_per_wav
 
   if constexpr (!MAT) load_tables_rep(TR, a.T0);
   __syncthreads();
+  // domain 0 and block indices below 2^32 (n <= 32768): round 1's fixed part once per workgroup
+  uint32_t fx[6];
+  if constexpr (!MAT) aes_round1_fixed_rep(TR, off0, off2, rk, rkr, 0u, fx);
 
   v4i acc[RG][CG][2];
 #pragma unroll
@@ -596,9 +721,9 @@ __global__ void __launch_bounds__(1024) k_prod_stream(ProdArgs a, int ks_per_wav
                 w[4] = v1.x; w[5] = v1.y; w[6] = v1.z; w[7] = v1.w;
               }
             } else {
-              const uint64_t b = ((uint64_t)col * n + k) >> 3;
-              aes_ctr_block_rep(TR, off0, off2, rk, rkr, 0u, b, w);
-              if (k + 8 < n) aes_ctr_block_rep(TR, off0, off2, rk, rkr, 0u, b + 1, w + 4);
+              const uint32_t b = (uint32_t)(((uint64_t)col * n + k) >> 3);
+              aes_ctr_block_rep_fixed(TR, off0, off2, rk, rkr, fx, b, w);
+              if (k + 8 < n) aes_ctr_block_rep_fixed(TR, off0, off2, rk, rkr, fx, b + 1, w + 4);
             }
           } else if (col < n + 8 && a.Bt) {
             const uint4 v0 = *(const uint4*)(a.Bt + 2 * ((size_t)(col - n) * n + k));
@@ -634,9 +759,9 @@ __global__ void __launch_bounds__(1024) k_prod_stream(ProdArgs a, int ks_per_wav
               w[4] = v1.x; w[5] = v1.y; w[6] = v1.z; w[7] = v1.w;
             }
           } else {
-            const uint64_t b = ((uint64_t)j * n + i0) >> 3;
-            aes_ctr_block_rep(TR, off0, off2, rk, rkr, 0u, b, w);
-            if (i0 + 8 < n) aes_ctr_block_rep(TR, off0, off2, rk, rkr, 0u, b + 1, w + 4);
+            const uint32_t b = (uint32_t)(((uint64_t)j * n + i0) >> 3);
+            aes_ctr_block_rep_fixed(TR, off0, off2, rk, rkr, fx, b, w);
+            if (i0 + 8 < n) aes_ctr_block_rep_fixed(TR, off0, off2, rk, rkr, fx, b + 1, w + 4);
           }
         }
         uint32_t lo[4], hi[4];
@@ -772,6 +897,9 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
   if constexpr (TAB == 1) load_tables(T, a.T0);
   if constexpr (TAB == 2) load_tables_q(T, a.T0);
   __syncthreads();
+  // domain 0 and block indices below 2^32 (n <= 32768): round 1's fixed part once per workgroup
+  uint32_t fx[6];
+  if constexpr (TAB == 2) aes_round1_fixed_q(T, qoff, rk, rkr, 0u, fx);
 
   // ---- regenerate (or, unfused, copy) the strip ----
   // Item t = one AES block = 8 consecutive contraction rows of one column.  Items are
@@ -827,7 +955,7 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
       } else if constexpr (TAB == 1) {
         aes_ctr_block(T, rk, 0u, ((uint64_t)c * n + k) >> 3, w[j]);
       } else {
-        aes_ctr_block_q(T, qoff, rk, rkr, 0u, ((uint64_t)c * n + k) >> 3, w[j]);
+        aes_ctr_block_q_fixed(T, qoff, rk, rkr, fx, (uint32_t)(((uint64_t)c * n + k) >> 3), w[j]);
       }
     }
 #pragma unroll
