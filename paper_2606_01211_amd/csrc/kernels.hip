@@ -1432,7 +1432,11 @@ __device__ __forceinline__ uint32_t keccak_rc_half(int round, int parity) {
 }
 
 __device__ __forceinline__ void keccak_f1600_pair(uint32_t s[25], uint32_t p) {
-  const uint32_t sh1 = p ? 0u : 31u;  // rotation of the partner's C[x+1] by 1 (even half) or 0
+  // rotation of the partner's C[x+1] by 1 (even half) or 0.  Passed through a move the compiler
+  // cannot see into: knowing it is 0 or 31, it would turn each variable rotation into a constant
+  // one plus a select (two instructions instead of one).
+  uint32_t sh1;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(sh1) : "v"(p ? 0u : 31u));
   // Twelve rounds per iteration: few register moves for pi at the back edge (its position
   // cycle has length 24), and a body small enough to stay within 128 registers.
 #pragma unroll 12
