@@ -505,6 +505,44 @@ static int g_num_cus = 256;
 constexpr int SAMPLE_ILP = 4;   // AES blocks per lane per unit
 constexpr int SAMPLE_WAVES = 8; // waves per workgroup
 
+// Samples and stores the eight values of AES block lb of segment seg of instance inst.
+// Segments 0 and 1 are 8 x n matrices filled row by row, n/8 blocks per row: row = lb / nb
+// is taken as mulhi(2 lb, magic) with magic = floor(2^32 / (2 nb)) + 1, exact because
+// 2 lb < 2^16 and 2 nb <= 8192.  Row-major offsets reduce to 8 lb from the instance's base.
+template <int KT>
+__device__ __forceinline__ void sample_store(const SampleArgs& a, int inst, int seg, uint32_t lb,
+                                             uint32_t nb, uint32_t magic, const uint32_t o[4]) {
+  uint32_t h[4];  // samples 2k, 2k+1 as int16 halves
+#pragma unroll
+  for (int q = 0; q < 4; ++q) h[q] = sample_pair<KT>(o[q], a.T2, a.K);
+  const uint32_t p0 = __builtin_amdgcn_perm(h[1], h[0], 0x06040200u);  // low bytes = int8 samples
+  const uint32_t p1 = __builtin_amdgcn_perm(h[3], h[2], 0x06040200u);
+  const uint2 v = make_uint2(p0, p1);
+  if (seg == 0) {
+    int8_t* dst;
+    if (a.x_frag) {
+      // frag_offset(8 inst + row, col, ldx / 64) with the instance's rows 8 (inst & 1) .. +7
+      // of 16-row group inst >> 1; eight consecutive columns stay inside one 16-byte slot
+      const uint32_t row = __umulhi(2u * lb, magic), col = 8u * (lb - row * nb);
+      const uint32_t r16 = ((uint32_t)(inst & 1) << 3) | row;
+      dst = a.X + (size_t)(inst >> 1) * (size_t)(a.ldx >> 6) * 1024u +
+            (((col >> 6) * 64u + (r16 | (((col & 63u) >> 4) << 4))) * 16u + (col & 15u));
+    } else if (a.ldx == a.n) {
+      dst = a.X + (size_t)inst * 8 * a.n + 8u * lb;
+    } else {
+      const uint32_t row = __umulhi(2u * lb, magic), col = 8u * (lb - row * nb);
+      dst = a.X + ((size_t)inst * 8 + row) * a.ldx + col;
+    }
+    *(uint2*)dst = v;
+    if (a.X16)  // int16 copy, row-major 8 x n: byte offset 2 (row n + col) = 16 lb
+      *(uint4*)(a.X16 + (size_t)inst * a.x16_stride + 16u * lb) = make_uint4(h[0], h[1], h[2], h[3]);
+  } else if (seg == 1) {
+    *(uint2*)(a.E + (size_t)inst * 8 * a.n + 8u * lb) = v;
+  } else {
+    *(uint2*)(a.E2 + (size_t)inst * 64 + 8u * lb) = v;
+  }
+}
+
 template <int KT>
 __global__ void __launch_bounds__(64 * SAMPLE_WAVES) k_sample(SampleArgs a, int count) {
   __shared__ uint32_t TR[TR_WORDS];
@@ -513,6 +551,7 @@ __global__ void __launch_bounds__(64 * SAMPLE_WAVES) k_sample(SampleArgs a, int 
   const int lane = threadIdx.x & 63;
   const uint32_t off0 = (uint32_t)(lane & 31) << 2, off2 = off0 + 128;
   const int n = a.n;
+  const uint32_t nb = (uint32_t)n >> 3, magic = 0xffffffffu / (2u * nb) + 1u;
   const int total = 2 * n + (a.nseg == 3 ? 8 : 0);  // AES blocks per instance
   // Work unit = 64 * SAMPLE_ILP consecutive blocks of one instance, taken by one wave, so
   // that the instance's round keys are wave-uniform (scalar registers).
@@ -535,59 +574,39 @@ __global__ void __launch_bounds__(64 * SAMPLE_WAVES) k_sample(SampleArgs a, int 
       }
     }
     uint32_t o[SAMPLE_ILP][4];
-    int tt[SAMPLE_ILP];
-    // A unit inside one segment (the usual case) has a wave-uniform domain word: round 1's
-    // fixed lookups are done once for its blocks.
     const int t_first = chunk * per_unit, t_last = min(t_first + per_unit - 1, total - 1);
     const int seg_first = t_first < n ? 0 : (t_first < 2 * n ? 1 : 2);
     const int seg_last = t_last < n ? 0 : (t_last < 2 * n ? 1 : 2);
     if (seg_first == seg_last) {
+      // A unit inside one segment (the usual case) has a wave-uniform domain word: round 1's
+      // fixed lookups are done once for its blocks, and the segment's stores are uniform.
       uint32_t fx[6];
       aes_round1_fixed_rep(TR, off0, off2, rk, rkr, bswap32((uint32_t)(seg_first + 1)), fx);
 #pragma unroll
       for (int j = 0; j < SAMPLE_ILP; ++j) {
         const int t = t_first + j * 64 + lane;
-        tt[j] = t;
         const int tc = t < total ? t : total - 1;
         aes_ctr_block_rep_fixed(TR, off0, off2, rk, rkr, fx, (uint32_t)(tc - seg_first * n), o[j]);
       }
-    } else {
 #pragma unroll
       for (int j = 0; j < SAMPLE_ILP; ++j) {
         const int t = t_first + j * 64 + lane;
-        tt[j] = t;
-        const int tc = t < total ? t : total - 1;
-        const int seg = tc < n ? 0 : (tc < 2 * n ? 1 : 2);
-        const int lb = tc - seg * n;
-        aes_ctr_block_rep(TR, off0, off2, rk, rkr, bswap32((uint32_t)(seg + 1)), (uint64_t)lb, o[j]);
+        if (t <= t_last) sample_store<KT>(a, inst, seg_first, (uint32_t)(t - seg_first * n), nb, magic, o[j]);
       }
-    }
+    } else {
+      int seg[SAMPLE_ILP];
 #pragma unroll
-    for (int j = 0; j < SAMPLE_ILP; ++j) {
-      const int t = tt[j];
-      if (t >= total) continue;
-      const int seg = t < n ? 0 : (t < 2 * n ? 1 : 2);
-      const int lb = t - seg * n;
-      uint32_t h[4];  // samples 2k, 2k+1 as int16 halves
+      for (int j = 0; j < SAMPLE_ILP; ++j) {
+        const int t = t_first + j * 64 + lane;
+        const int tc = t < total ? t : total - 1;
+        seg[j] = tc < n ? 0 : (tc < 2 * n ? 1 : 2);
+        aes_ctr_block_rep(TR, off0, off2, rk, rkr, bswap32((uint32_t)(seg[j] + 1)),
+                          (uint64_t)(tc - seg[j] * n), o[j]);
+      }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) h[q] = sample_pair<KT>(o[j][q], a.T2, a.K);
-      const uint32_t p0 = __builtin_amdgcn_perm(h[1], h[0], 0x06040200u);  // low bytes = int8 samples
-      const uint32_t p1 = __builtin_amdgcn_perm(h[3], h[2], 0x06040200u);
-      const int w0 = 8 * lb;
-      if (seg == 0) {
-        const int row = w0 / n, col = w0 - row * n;
-        // eight consecutive columns (col is a multiple of 8) stay inside one 16-byte slot
-        const int grow = inst * 8 + row;
-        *(uint2*)(a.X + (a.x_frag ? frag_offset(grow, col, a.ldx >> 6) : (size_t)grow * a.ldx + col)) =
-            make_uint2(p0, p1);
-        if (a.X16)
-          *(uint4*)(a.X16 + (size_t)inst * a.x16_stride + 2 * ((size_t)row * n + col)) =
-              make_uint4(h[0], h[1], h[2], h[3]);
-      } else if (seg == 1) {
-        const int row = w0 / n, col = w0 - row * n;
-        *(uint2*)(a.E + ((size_t)inst * 8 + row) * n + col) = make_uint2(p0, p1);
-      } else {
-        *(uint2*)(a.E2 + (size_t)inst * 64 + w0) = make_uint2(p0, p1);
+      for (int j = 0; j < SAMPLE_ILP; ++j) {
+        const int t = t_first + j * 64 + lane;
+        if (t < total) sample_store<KT>(a, inst, seg[j], (uint32_t)(t - seg[j] * n), nb, magic, o[j]);
       }
     }
   }
