@@ -554,27 +554,18 @@ __global__ void __launch_bounds__(64 * SAMPLE_WAVES) k_sample(SampleArgs a, int 
   const uint32_t nb = (uint32_t)n >> 3, magic = 0xffffffffu / (2u * nb) + 1u;
   const int total = 2 * n + (a.nseg == 3 ? 8 : 0);  // AES blocks per instance
   // Work unit = 64 * SAMPLE_ILP consecutive blocks of one instance, taken by one wave, so
-  // that the instance's round keys are wave-uniform.  Each wave takes a contiguous range of
-  // units and loads an instance's keys once for all of its units in that range.
+  // that the instance's round keys are wave-uniform (scalar registers).
   const int per_unit = 64 * SAMPLE_ILP;
   const int units_per_inst = (total + per_unit - 1) / per_unit;
   const int n_units = units_per_inst * count;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int nwaves = gridDim.x * SAMPLE_WAVES;
-  const int per_wave = (n_units + nwaves - 1) / nwaves;
-  const int u_begin = (blockIdx.x * SAMPLE_WAVES + wave) * per_wave;
-  const int u_end = min(u_begin + per_wave, n_units);
-  RoundKeys rk;
-  uint32_t rkr[36];
-  int key_inst = -1;
-  for (int u = u_begin; u < u_end; ++u) {
+  for (int u = blockIdx.x * SAMPLE_WAVES + wave; u < n_units; u += nwaves) {
     const int inst = u / units_per_inst, chunk = u - inst * units_per_inst;
-    if (inst != key_inst) {
-      rk = load_rk(a.rk + (size_t)inst * 44);
+    const RoundKeys rk = load_rk(a.rk + (size_t)inst * 44);
+    uint32_t rkr[36];
 #pragma unroll
-      for (int i = 0; i < 36; ++i) rkr[i] = rotl32(rk[4 + i], 24);
-      key_inst = inst;
-    }
+    for (int i = 0; i < 36; ++i) rkr[i] = rotl32(rk[4 + i], 24);
     if (chunk == 0 && a.ldx > n) {  // zero the padding columns of segment 0
       const int pad = a.ldx - n;
       for (int idx = lane; idx < 8 * pad; idx += 64) {
