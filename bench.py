@@ -8,7 +8,10 @@ versus plain (one instance per call), with p50/p99 latencies.
 One step = KeyGen of a fresh key pair + lwe_encaps_batch(4096) + lwe_decaps_batch(4096) on
 device-resident buffers: every stage of the hot path (A expansion, sampling, all products,
 decoding, re-encryption + comparison, FO hashing) runs inside the timed region.
-`value` = 4096 * steps / wall time of the timed steps.
+`value` = 4096 * steps / wall time of the timed steps, with --streams independent steps in
+flight (one library context and HIP stream per lane; each lane's context keeps all of its work
+on that one stream, so every lane has a hardware queue of its own).  `serial` is the same run
+on one lane, whose decapsulations overlap their ciphertext hash on the context's second stream.
 
 Also reported: the plain path (lwe_encaps / lwe_decaps one instance per call), per-kernel
 device time from HIP events recorded by the library on its streams, the roofline of the
@@ -51,20 +54,23 @@ def pct(xs, q):
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=128,
+    ap.add_argument("--steps", type=int, default=144,
                     help="timed steps (spread round-robin over the streams; a multiple of --streams keeps "
                          "the lanes even)")
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--n", type=int, default=1344)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--plain", type=int, default=300, help="plain encaps and decaps calls timed one by one")
-    ap.add_argument("--streams", type=int, default=8,
+    ap.add_argument("--streams", type=int, default=12,
                     help="independent steps in flight (one library context and HIP stream each); the "
                          "serial rate (one stream) is always measured too")
+    ap.add_argument("--lane-side-stream", action="store_true",
+                    help="let the lanes' decapsulations hash on their context's second stream too "
+                         "(two streams per lane)")
     ap.add_argument("--hw-queues", type=int, default=0,
                     help="HIP hardware queues of this process (GPU_MAX_HW_QUEUES, at most 32; default "
-                         "2 * streams + 2): each step in flight runs on its context's two streams, and "
-                         "each of them then gets a queue of its own instead of waiting behind another "
+                         "streams + 3, or 2 * streams + 2 with --lane-side-stream): every stream in "
+                         "use then gets a queue of its own instead of waiting behind another "
                          "stream's packets")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="budget of the CPU oracle leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
@@ -175,7 +181,8 @@ def main():
     if args.copy_calibration:
         return copy_calibration()
     # before anything initialises the GPU runtime
-    hwq = args.hw_queues if args.hw_queues > 0 else 2 * max(1, args.streams) + 2
+    S = max(1, args.streams)
+    hwq = args.hw_queues if args.hw_queues > 0 else (2 * S + 2 if args.lane_side_stream else S + 3)
     os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, max(1, hwq)))
     if args.gpus != 1:
         print("bench.py measures one GPU: the KEM hot path here runs on a single MI355X; "
@@ -194,10 +201,13 @@ def main():
     p = L.params(pid)
     B = args.batch
     K, W = args.steps, args.warmup
-    S = max(1, args.streams)
     ctxs = [L.Context(0) for _ in range(S)]
-    # each lane runs on its context's own stream (the context's second stream overlaps the
-    # decapsulation hash): two streams per lane, each on a hardware queue of its own
+    # each lane runs on its context's own stream.  Lane 0 also times the serial rate, with the
+    # decapsulation hash overlapped on its context's second stream; in the pipelined run every
+    # lane keeps all of its work on its one stream (unless --lane-side-stream), so the lanes
+    # need one hardware queue each and more of them fit before queues are shared
+    for c in ctxs[1:]:
+        c.set_side_stream(args.lane_side_stream)
     streams = [torch.cuda.ExternalStream(c.stream_handle, device=dev) for c in ctxs]
     ctx = ctxs[0]
     if args.unfused:
@@ -287,6 +297,7 @@ def main():
     wall1, step_ms1, prof1 = timed(1, W)
     serial_value = K * B / wall1
     if S > 1:
+        ctxs[0].set_side_stream(args.lane_side_stream)
         wall, step_ms, prof = timed(S, W + K)
     else:
         wall, step_ms, prof = wall1, step_ms1, prof1
@@ -445,6 +456,7 @@ def main():
         "batch_latency_ms": {"p50": pct(step_ms, 50), "p99": pct(step_ms, 99)},
         "streams": S,
         "hw_queues": int(os.environ["GPU_MAX_HW_QUEUES"]),
+        "lane_side_stream": bool(args.lane_side_stream),
         "serial": {"value": serial_value, "ms_per_step": 1e3 * wall1 / K,
                    "batch_latency_ms": {"p50": pct(step_ms1, 50), "p99": pct(step_ms1, 99)}},
         "plain": {"value": plain_rate, "unit": "encaps+decaps/s",

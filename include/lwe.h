@@ -80,10 +80,18 @@ size_t lwe_ctx_device_bytes(const lwe_ctx* ctx);
 /* The context's own HIP stream (a hipStream_t; owned by the context, valid until
  * lwe_ctx_destroy).  Calls given a NULL stream run on it and return once it has finished;
  * a caller may also pass it explicitly to run asynchronously, so that each context's work
- * uses only the context's two streams (this one and the internal one that overlaps the
- * decapsulation hash), which keeps HIP's stream-to-hardware-queue mapping predictable when
- * several contexts run concurrently.  NULL for a NULL context. */
+ * uses only the context's streams (this one and, see lwe_ctx_set_side_stream, the internal
+ * one that overlaps the decapsulation hash), which keeps HIP's stream-to-hardware-queue
+ * mapping predictable when several contexts run concurrently.  NULL for a NULL context. */
 void* lwe_ctx_stream(lwe_ctx* ctx);
+/* Whether lwe_decaps_batch hashes the received ciphertexts (the H(ct) of the FO transform,
+ * Alg. 5) on the context's second stream, concurrently with the decryption and
+ * re-encryption (enable = 1, the default), or first on the call's own stream (0).  The
+ * second stream shortens one call; with 0 a context uses a single stream, and so a single
+ * HIP hardware queue, which lets more contexts run concurrently before queues are shared.
+ * The second stream is created by the first call that needs it.  Results are identical
+ * either way.  Returns LWE_EINVAL for a NULL context or an enable other than 0 or 1. */
+int lwe_ctx_set_side_stream(lwe_ctx* ctx, int enable);
 const char* lwe_strerror(int status);
 
 /* Parameter registry: id of the set for lattice dimension n, or a negative lwe_status. */

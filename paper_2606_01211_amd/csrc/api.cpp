@@ -33,8 +33,9 @@ struct lwe_ctx {
   int device = 0;
   hipStream_t own = nullptr;
   // second stream for work that overlaps the main one inside a call (decaps hashes the
-  // received ciphertexts while it decrypts and re-encrypts them)
+  // received ciphertexts while it decrypts and re-encrypts them); created on first use
   hipStream_t side = nullptr;
+  bool use_side = true;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   size_t budget = 0;  // 0 = unlimited
   size_t held = 0;
@@ -473,7 +474,6 @@ int lwe_ctx_create(lwe_ctx** out, int device, size_t hbm_budget_bytes) {
   unsigned hc = std::thread::hardware_concurrency();
   c->host_threads = (int)std::max(1u, std::min(hc, 16u));
   if (hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess ||
-      hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
       hipMalloc(&c->d_T0, 1024) != hipSuccess ||
@@ -508,6 +508,12 @@ void lwe_ctx_destroy(lwe_ctx* c) {
 
 size_t lwe_ctx_device_bytes(const lwe_ctx* c) { return c ? c->held + 1024 : 0; }
 void* lwe_ctx_stream(lwe_ctx* c) { return c ? (void*)c->own : nullptr; }
+
+int lwe_ctx_set_side_stream(lwe_ctx* c, int enable) {
+  if (!c || (enable != 0 && enable != 1)) return LWE_EINVAL;
+  c->use_side = enable != 0;
+  return LWE_OK;
+}
 
 int lwe_prof_enable(lwe_ctx* c, int on) {
   if (!c) return LWE_EINVAL;
@@ -878,18 +884,27 @@ int lwe_decaps_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* sk, const
     }
   } else {
     // H(ct) of the received ciphertexts does not depend on the decryption: it runs on the
-    // side stream while the main stream decrypts and re-encrypts.
+    // side stream while the main stream decrypts and re-encrypts (or first, on the main
+    // stream, when the context keeps all of its work on one stream).
     uint8_t* dhct;
     LWE_CHECK(ensure_t(c, B_HCT, count * 32, &dhct));
-    HIP_CHECK(hipEventRecord(c->ev_fork, s));
-    HIP_CHECK(hipStreamWaitEvent(c->side, c->ev_fork, 0));
-    KLAUNCH("hash_records", c->side, launch_hash_records((int)count, dct, p.ct_bytes, p.ct_bytes, dhct, c->side));
-    HIP_CHECK(hipEventRecord(c->ev_join, c->side));
+    if (c->use_side && !c->side && hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
+      c->side = nullptr;
+      (void)hipGetLastError();
+      return LWE_EDEVICE;
+    }
+    hipStream_t hs = c->use_side ? c->side : s;
+    if (c->use_side) {
+      HIP_CHECK(hipEventRecord(c->ev_fork, s));
+      HIP_CHECK(hipStreamWaitEvent(c->side, c->ev_fork, 0));
+    }
+    KLAUNCH("hash_records", hs, launch_hash_records((int)count, dct, p.ct_bytes, p.ct_bytes, dhct, hs));
+    if (c->use_side) HIP_CHECK(hipEventRecord(c->ev_join, c->side));
     KLAUNCH("fo_coins", s, launch_fo_coins((int)count, dsk + off_pkh, dmu2, mb, (int)mb, dcoins, dkp, s));
     KLAUNCH("expand_keys", s, launch_expand_keys(dcoins, 16, (int)count, c->d_T0, drk, s));
     KLAUNCH("fill", s, launch_fill_u32(dflags, count, 0, s));
     LWE_CHECK(encrypt_core(c, pid, p, count, dsk + off_pk, drk, dmu2, mb, nullptr, dct, dflags, s));
-    HIP_CHECK(hipStreamWaitEvent(s, c->ev_join, 0));
+    if (c->use_side) HIP_CHECK(hipStreamWaitEvent(s, c->ev_join, 0));
     KLAUNCH("final_ss", s, launch_final_ss((int)count, dflags, dkp, dsk + off_z, dhct, oss.dev, s));
   }
   LWE_CHECK(finish_out(oss, s));

@@ -24,6 +24,9 @@ def test_exports_every_declared_symbol():
     for name in decl:
         assert hasattr(L, name), name
     assert sorted(lwe.EXPORTS) == decl
+    # argument checks that touch no device
+    assert L.lwe_ctx_set_side_stream(None, 1) == lwe.LWE_EINVAL
+    assert L.lwe_ctx_stream(None) is None
 
 
 @pytest.mark.parametrize("n", [640, 976, 1344, 4096, 8192, 16384, 32768])

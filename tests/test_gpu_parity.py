@@ -432,6 +432,39 @@ def test_context_stream_lanes(orc):
             c.close()
 
 
+def test_decaps_side_stream_off_and_on(orc):
+    """lwe_ctx_set_side_stream: a batched decapsulation with the ciphertext hash on the call's
+    own stream (0) and on the context's second stream (1) gives the oracle's shared secrets,
+    for valid and tampered ciphertexts alike, in either order."""
+    lib = L()
+    lp, op = _pair(orc, 640)
+    g = lwe_inputs.rng(0, 2200)
+    pk, sk = _keypair(orc, op, g)
+    count = 96  # above the host-hash limit: the device hash path
+    mus = lwe_inputs.messages(g, count, op.mu_bytes)
+    c = lib.Context(0)
+    try:
+        assert c._lib.lwe_ctx_set_side_stream(c._h, 2) == lib.lwe.LWE_EINVAL
+        ct = np.zeros((count, op.ct_bytes), np.uint8)
+        ss = np.zeros((count, 32), np.uint8)
+        c.encaps_batch(lp.pid, count, pk, mus, ct, ss)
+        for i in range(1, count, 2):
+            ct[i, (i * 37) % op.ct_bytes] ^= 1 << (i % 8)
+        want = [orc.kem_decaps(op, sk, ct[i].tobytes()) for i in range(count)]
+        for enable in (False, True, False):
+            c.set_side_stream(enable)
+            say("decaps side stream", enable)
+            ss2 = np.zeros((count, 32), np.uint8)
+            c.decaps_batch(lp.pid, count, sk, ct, ss2)
+            for i in range(count):
+                oss, ok = want[i]
+                assert ok == (i % 2 == 0), (enable, i)
+                assert ss2[i].tobytes() == oss, (enable, i)
+            assert np.array_equal(ss2[0::2], ss[0::2])
+    finally:
+        c.close()
+
+
 def test_strip_split_k_8192(ctx, orc):
     """A batch of 32 encryptions at n = 8192: the strip product with its contraction split in
     two K chunks (S' in fragment order, partial sums accumulated and finished by k_finalize),
