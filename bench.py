@@ -11,7 +11,9 @@ decoding, re-encryption + comparison, FO hashing) runs inside the timed region.
 `value` = 4096 * steps / wall time of the timed steps, with --streams independent steps in
 flight (one library context and HIP stream per lane; each lane's context keeps all of its work
 on that one stream, so every lane has a hardware queue of its own).  `serial` is the same run
-on one lane, whose decapsulations overlap their ciphertext hash on the context's second stream.
+on one lane, whose decapsulations overlap their ciphertext hash on the context's second stream
+and whose SHA3 kernels hash each record on two lanes (shorter latency); the pipelined lanes hash
+one record per thread (less work per record).
 
 Also reported: the plain path (lwe_encaps / lwe_decaps one instance per call), per-kernel
 device time from HIP events recorded by the library on its streams, the roofline of the
@@ -67,6 +69,8 @@ def parse():
     ap.add_argument("--lane-side-stream", action="store_true",
                     help="let the lanes' decapsulations hash on their context's second stream too "
                          "(two streams per lane)")
+    ap.add_argument("--lane-hash-lanes", type=int, default=1, choices=(1, 2),
+                    help="lanes per record of the pipelined lanes' SHA3 kernels (the serial run uses 2)")
     ap.add_argument("--hw-queues", type=int, default=0,
                     help="HIP hardware queues of this process (GPU_MAX_HW_QUEUES, at most 32; default "
                          "streams + 3, or 2 * streams + 2 with --lane-side-stream): every stream in "
@@ -208,6 +212,7 @@ def main():
     # need one hardware queue each and more of them fit before queues are shared
     for c in ctxs[1:]:
         c.set_side_stream(args.lane_side_stream)
+        c.set_hash_lanes(args.lane_hash_lanes)
     streams = [torch.cuda.ExternalStream(c.stream_handle, device=dev) for c in ctxs]
     ctx = ctxs[0]
     if args.unfused:
@@ -298,6 +303,7 @@ def main():
     serial_value = K * B / wall1
     if S > 1:
         ctxs[0].set_side_stream(args.lane_side_stream)
+        ctxs[0].set_hash_lanes(args.lane_hash_lanes)
         wall, step_ms, prof = timed(S, W + K)
     else:
         wall, step_ms, prof = wall1, step_ms1, prof1
@@ -457,6 +463,7 @@ def main():
         "streams": S,
         "hw_queues": int(os.environ["GPU_MAX_HW_QUEUES"]),
         "lane_side_stream": bool(args.lane_side_stream),
+        "lane_hash_lanes": int(args.lane_hash_lanes),
         "serial": {"value": serial_value, "ms_per_step": 1e3 * wall1 / K,
                    "batch_latency_ms": {"p50": pct(step_ms1, 50), "p99": pct(step_ms1, 99)}},
         "plain": {"value": plain_rate, "unit": "encaps+decaps/s",

@@ -92,6 +92,13 @@ void* lwe_ctx_stream(lwe_ctx* ctx);
  * The second stream is created by the first call that needs it.  Results are identical
  * either way.  Returns LWE_EINVAL for a NULL context or an enable other than 0 or 1. */
 int lwe_ctx_set_side_stream(lwe_ctx* ctx, int enable);
+/* Layout of the batched SHA3-256 (FIPS 202) hashing of records in KeyGen, Encaps and Decaps
+ * (H(pk), H(ct) of the FO transform, Alg. 4-5): lanes = 2 (the default) hashes each record on
+ * two lanes, each holding one bit-interleaved half of the state, which halves one call's hash
+ * latency; lanes = 1 hashes one record per thread, about a fifth less work per record at 1.6
+ * times the latency, which suits many contexts running at once.  Digests are identical either
+ * way.  Returns LWE_EINVAL for a NULL context or lanes other than 1 or 2. */
+int lwe_ctx_set_hash_lanes(lwe_ctx* ctx, int lanes);
 const char* lwe_strerror(int status);
 
 /* Parameter registry: id of the set for lattice dimension n, or a negative lwe_status. */

@@ -36,6 +36,7 @@ struct lwe_ctx {
   // received ciphertexts while it decrypts and re-encrypts them); created on first use
   hipStream_t side = nullptr;
   bool use_side = true;
+  int hash_lanes = 2;  // lanes per record of the batched SHA3 kernel (2 or 1)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   size_t budget = 0;  // 0 = unlimited
   size_t held = 0;
@@ -509,6 +510,12 @@ void lwe_ctx_destroy(lwe_ctx* c) {
 size_t lwe_ctx_device_bytes(const lwe_ctx* c) { return c ? c->held + 1024 : 0; }
 void* lwe_ctx_stream(lwe_ctx* c) { return c ? (void*)c->own : nullptr; }
 
+int lwe_ctx_set_hash_lanes(lwe_ctx* c, int lanes) {
+  if (!c || (lanes != 1 && lanes != 2)) return LWE_EINVAL;
+  c->hash_lanes = lanes;
+  return LWE_OK;
+}
+
 int lwe_ctx_set_side_stream(lwe_ctx* c, int enable) {
   if (!c || (enable != 0 && enable != 1)) return LWE_EINVAL;
   c->use_side = enable != 0;
@@ -685,7 +692,7 @@ int lwe_keygen_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* seedA, co
   } else {
     uint8_t* dh;
     LWE_CHECK(ensure_t(c, B_HCT, count * 32, &dh));
-    KLAUNCH("hash_records", s, launch_hash_records((int)count, opk.dev, p.pk_bytes, p.pk_bytes, dh, s));
+    KLAUNCH("hash_records", s, launch_hash_records((int)count, opk.dev, p.pk_bytes, p.pk_bytes, dh, c->hash_lanes, s));
     HIP_CHECK(hipMemcpy2DAsync(osk.dev + off_pkh, p.sk_bytes, dh, 32, 32, count, hipMemcpyDeviceToDevice, s));
   }
   LWE_CHECK(finish_out(opk, s));
@@ -774,7 +781,7 @@ int lwe_encaps_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* pk, const
   } else {
     uint8_t* dhct;
     LWE_CHECK(ensure_t(c, B_HCT, count * 32, &dhct));
-    KLAUNCH("hash_records", s, launch_hash_records((int)count, oct.dev, p.ct_bytes, p.ct_bytes, dhct, s));
+    KLAUNCH("hash_records", s, launch_hash_records((int)count, oct.dev, p.ct_bytes, p.ct_bytes, dhct, c->hash_lanes, s));
     KLAUNCH("final_ss", s, launch_final_ss((int)count, nullptr, dkp, nullptr, dhct, oss.dev, s));
   }
   LWE_CHECK(finish_out(oct, s));
@@ -898,7 +905,7 @@ int lwe_decaps_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* sk, const
       HIP_CHECK(hipEventRecord(c->ev_fork, s));
       HIP_CHECK(hipStreamWaitEvent(c->side, c->ev_fork, 0));
     }
-    KLAUNCH("hash_records", hs, launch_hash_records((int)count, dct, p.ct_bytes, p.ct_bytes, dhct, hs));
+    KLAUNCH("hash_records", hs, launch_hash_records((int)count, dct, p.ct_bytes, p.ct_bytes, dhct, c->hash_lanes, hs));
     if (c->use_side) HIP_CHECK(hipEventRecord(c->ev_join, c->side));
     KLAUNCH("fo_coins", s, launch_fo_coins((int)count, dsk + off_pkh, dmu2, mb, (int)mb, dcoins, dkp, s));
     KLAUNCH("expand_keys", s, launch_expand_keys(dcoins, 16, (int)count, c->d_T0, drk, s));
@@ -1042,7 +1049,7 @@ int lwe_test_sha3(lwe_ctx* c, size_t count, size_t len, const uint8_t* in, uint8
   LWE_CHECK(stage_in(c, B_CT, in, count * len, s, &din));
   OutStage o;
   LWE_CHECK(stage_out(c, B_TEST, out, count * 32, o));
-  KLAUNCH("hash_records", s, launch_hash_records((int)count, din, len, len, o.dev, s));
+  KLAUNCH("hash_records", s, launch_hash_records((int)count, din, len, len, o.dev, c->hash_lanes, s));
   LWE_CHECK(finish_out(o, s));
   HIP_CHECK(hipStreamSynchronize(s));
   return LWE_OK;

@@ -112,8 +112,9 @@ hipError_t launch_finalize(const ProdArgs& a, hipStream_t s);
 hipError_t launch_decrypt(const DecArgs& a, hipStream_t s);
 hipError_t launch_fo_coins(int count, const uint8_t* pkh, const uint8_t* mu, size_t mu_stride,
                            int mu_bytes, uint8_t* coins, uint8_t* kprime, hipStream_t s);
+// lanes: 2 = two lanes per record (k_hash_records), 1 = one record per thread
 hipError_t launch_hash_records(int count, const uint8_t* in, size_t stride, size_t len,
-                               uint8_t* out, hipStream_t s);
+                               uint8_t* out, int lanes, hipStream_t s);
 hipError_t launch_final_ss(int count, const uint32_t* flags, const uint8_t* kprime,
                            const uint8_t* z, const uint8_t* hct, uint8_t* ss, hipStream_t s);
 hipError_t init_kernels();

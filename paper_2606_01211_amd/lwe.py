@@ -24,7 +24,7 @@ LWE_OK, LWE_EINVAL, LWE_ENOMEM, LWE_EDEVICE, LWE_EUNSUPPORTED = 0, -1, -2, -3, -
 # every symbol include/lwe.h declares
 EXPORTS = [
     "lwe_ctx_create", "lwe_ctx_destroy", "lwe_ctx_device_bytes", "lwe_ctx_stream",
-    "lwe_ctx_set_side_stream", "lwe_strerror",
+    "lwe_ctx_set_side_stream", "lwe_ctx_set_hash_lanes", "lwe_strerror",
     "lwe_param_id", "lwe_param_register", "lwe_param_get", "lwe_pk_bytes", "lwe_sk_bytes",
     "lwe_ct_bytes", "lwe_mu_bytes", "lwe_cdf_table",
     "lwe_keygen", "lwe_encaps", "lwe_decaps",
@@ -90,6 +90,7 @@ def lib() -> C.CDLL:
         "lwe_ctx_device_bytes": (sz, [vp]),
         "lwe_ctx_stream": (vp, [vp]),
         "lwe_ctx_set_side_stream": (i32, [vp, i32]),
+        "lwe_ctx_set_hash_lanes": (i32, [vp, i32]),
         "lwe_strerror": (C.c_char_p, [i32]),
         "lwe_param_id": (i32, [u32]),
         "lwe_param_register": (i32, [u32, u32, u32, u32, C.c_double]),
@@ -276,6 +277,11 @@ class Context:
         overlapping the re-encryption (True, the default), or on the call's own stream, so
         that the context uses one stream only (False)."""
         _check(self._lib.lwe_ctx_set_side_stream(self._h, 1 if enable else 0), "lwe_ctx_set_side_stream")
+
+    def set_hash_lanes(self, lanes: int) -> None:
+        """Lanes per record of the batched SHA3 hashing: 2 (default, shorter latency) or 1 (less
+        work per record, for many contexts at once)."""
+        _check(self._lib.lwe_ctx_set_hash_lanes(self._h, int(lanes)), "lwe_ctx_set_hash_lanes")
 
     # ---- tuning ----
     def set_tuning(self, pid: int, col_groups=0, row_groups=0, m_chunks=0, host_hash_max=0, a_source=0):

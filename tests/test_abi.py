@@ -26,6 +26,7 @@ def test_exports_every_declared_symbol():
     assert sorted(lwe.EXPORTS) == decl
     # argument checks that touch no device
     assert L.lwe_ctx_set_side_stream(None, 1) == lwe.LWE_EINVAL
+    assert L.lwe_ctx_set_hash_lanes(None, 1) == lwe.LWE_EINVAL
     assert L.lwe_ctx_stream(None) is None
 
 

@@ -78,14 +78,22 @@ def test_sampler(ctx, orc, n):
         assert np.array_equal(out, orc.sample_stream(op, key, domain, word0, cnt))
 
 
+@pytest.mark.parametrize("lanes", [2, 1])
+@pytest.mark.parametrize("cnt", [5, 70])
 @pytest.mark.parametrize("length", [0, 1, 135, 136, 137, 1000, 21632])
-def test_device_sha3(ctx, length):
-    g = lwe_inputs.rng(0, 1300 + length)
-    cnt = 5
+def test_device_sha3(ctx, length, cnt, lanes):
+    """The batched SHA3-256 kernel in both layouts (two lanes per record, one record per
+    thread); lengths around the rate, unaligned records, and 70 records (a ragged second
+    wave for the one-per-thread layout)."""
+    g = lwe_inputs.rng(0, 1300 + length + cnt)
     data = lwe_inputs.random_bytes(g, cnt, max(1, length))[:, :length].copy()
     out = np.zeros((cnt, 32), np.uint8)
-    say("sha3", length)
-    ctx.test_sha3(cnt, length, data, out)
+    say("sha3", length, cnt, lanes)
+    ctx.set_hash_lanes(lanes)
+    try:
+        ctx.test_sha3(cnt, length, data, out)
+    finally:
+        ctx.set_hash_lanes(2)
     for i in range(cnt):
         assert out[i].tobytes() == H(data[i].tobytes())
 
@@ -461,6 +469,50 @@ def test_decaps_side_stream_off_and_on(orc):
                 assert ok == (i % 2 == 0), (enable, i)
                 assert ss2[i].tobytes() == oss, (enable, i)
             assert np.array_equal(ss2[0::2], ss[0::2])
+    finally:
+        c.close()
+
+
+def test_kem_one_lane_hash(orc):
+    """A context in the many-contexts configuration (one stream, one record per thread in the
+    SHA3 kernels): batched KeyGen (H(pk) on the device), Encaps and Decaps, valid and tampered
+    ciphertexts, against the oracle."""
+    lib = L()
+    lp, op = _pair(orc, 640)
+    g = lwe_inputs.rng(0, 2300)
+    kc = 20  # above the host-hash limit: device H(pk)
+    seedA, seedSK, z = lwe_inputs.keygen_seeds(g, kc)
+    c = lib.Context(0)
+    try:
+        c.set_side_stream(False)
+        c.set_hash_lanes(1)
+        pks = np.zeros((kc, op.pk_bytes), np.uint8)
+        sks = np.zeros((kc, op.sk_bytes), np.uint8)
+        say("one-lane hash keygen", kc)
+        c.keygen_batch(lp.pid, kc, seedA, seedSK, z, pks, sks)
+        for i in (0, kc - 1):
+            opk, osk = orc.kem_keygen(op, seedA[i].tobytes(), seedSK[i].tobytes(), z[i].tobytes())
+            assert pks[i].tobytes() == opk and sks[i].tobytes() == osk, i
+        pk, sk = pks[0].tobytes(), sks[0].tobytes()
+        count = 96
+        mus = lwe_inputs.messages(g, count, op.mu_bytes)
+        ct = np.zeros((count, op.ct_bytes), np.uint8)
+        ss = np.zeros((count, 32), np.uint8)
+        say("one-lane hash encaps", count)
+        c.encaps_batch(lp.pid, count, pk, mus, ct, ss)
+        for i in (0, 47, count - 1):
+            oct_, oss = orc.kem_encaps(op, pk, mus[i].tobytes())
+            assert ct[i].tobytes() == oct_ and ss[i].tobytes() == oss, i
+        for i in range(1, count, 2):
+            ct[i, (i * 53) % op.ct_bytes] ^= 1 << (i % 8)
+        ss2 = np.zeros((count, 32), np.uint8)
+        say("one-lane hash decaps", count)
+        c.decaps_batch(lp.pid, count, sk, ct, ss2)
+        for i in range(count):
+            oss, ok = orc.kem_decaps(op, sk, ct[i].tobytes())
+            assert ok == (i % 2 == 0), i
+            assert ss2[i].tobytes() == oss, i
+        assert c._lib.lwe_ctx_set_hash_lanes(c._h, 3) == lib.lwe.LWE_EINVAL
     finally:
         c.close()
 
