@@ -56,14 +56,14 @@ def pct(xs, q):
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=144,
+    ap.add_argument("--steps", type=int, default=140,
                     help="timed steps (spread round-robin over the streams; a multiple of --streams keeps "
                          "the lanes even)")
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--n", type=int, default=1344)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--plain", type=int, default=300, help="plain encaps and decaps calls timed one by one")
-    ap.add_argument("--streams", type=int, default=12,
+    ap.add_argument("--streams", type=int, default=14,
                     help="independent steps in flight (one library context and HIP stream each); the "
                          "serial rate (one stream) is always measured too")
     ap.add_argument("--lane-side-stream", action="store_true",
