@@ -169,9 +169,9 @@ int lwe_test_sha3(lwe_ctx* ctx, size_t count, size_t len, const uint8_t* in, uin
  * bracketed by a pair of HIP events on the stream it runs on.  lwe_prof_read synchronises
  * the recorded events and returns, for one kernel name ("sample", "prod_strip" (encryption),
  * "prod_strip_cmp" (the re-encryption and compare of a decapsulation),
- * "prod_stream", "finalize", "decrypt", "fo_coins", "expand_keys", "hash_records",
- * "final_ss", "fill", "keystream", "sample_stream", "expand_A"), the number of launches and their
- * summed device time since the last reset. */
+ * "prod_stream", "finalize", "decrypt", "fo_coins", "expand_keys", "hash_records" (either
+ * layout of lwe_ctx_set_hash_lanes), "final_ss", "fill", "keystream", "sample_stream",
+ * "expand_A"), the number of launches and their summed device time since the last reset. */
 int lwe_prof_enable(lwe_ctx* ctx, int on);
 int lwe_prof_reset(lwe_ctx* ctx);
 int lwe_prof_read(lwe_ctx* ctx, const char* kernel, uint64_t* launches, double* total_ms);
