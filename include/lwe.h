@@ -35,7 +35,10 @@
  *     host memory, and calls that hash on the host, synchronise the stream before returning;
  *     device outputs are valid once the stream has been synchronised.
  *   - The return value is an lwe_status.  On error, outputs are unspecified.
- *   - A context is not thread-safe: use one context per host thread.
+ *   - A context is not thread-safe: use one context per host thread.  Calls on one context
+ *     execute on the device in the order they are made, whatever streams they are given: a
+ *     call on a stream other than the previous call's first waits (hipStreamWaitEvent) for
+ *     the previous call's work, because calls reuse the context's device buffers.
  *   - Decaps of a malformed or tampered ciphertext is NOT an error: it returns LWE_OK and
  *     the implicit-rejection key H(z || H(ct)).
  */
@@ -70,13 +73,27 @@ typedef struct {
   size_t pk_bytes, sk_bytes, ct_bytes, mu_bytes;
 } lwe_param_info;
 
-/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the device working
- * memory the context may hold (0 = no limit); requests that need more fail with
- * LWE_ENOMEM.  Returns LWE_EDEVICE if the device cannot be used. */
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the device memory the
+ * context may hold, lwe_ctx_device_bytes (0 = no limit; otherwise at least 1024, the AES
+ * table every context keeps); requests that need more fail with LWE_ENOMEM.  Returns
+ * LWE_EDEVICE if the device cannot be used. */
 int lwe_ctx_create(lwe_ctx** out, int device, size_t hbm_budget_bytes);
 void lwe_ctx_destroy(lwe_ctx* ctx);
-/* Device working memory currently held by the context, in bytes. */
+/* Device memory currently held by the context, in bytes: its 1 KB AES table plus the
+ * working buffers, which grow to the largest request seen and are kept for reuse. */
 size_t lwe_ctx_device_bytes(const lwe_ctx* ctx);
+/* Changes the budget of lwe_ctx_create for later calls (0 = no limit, else >= 1024).  Memory
+ * already held is not released (see lwe_ctx_trim).  LWE_EINVAL for a NULL context or a
+ * budget below 1024. */
+int lwe_ctx_set_budget(lwe_ctx* ctx, size_t hbm_budget_bytes);
+/* Releases every working buffer of the context (lwe_ctx_device_bytes drops to 1024).  The
+ * release is ordered after the context's queued work; later calls allocate again. */
+int lwe_ctx_trim(lwe_ctx* ctx);
+/* Device bytes (lwe_ctx_device_bytes) that one call of `op` (0 KeyGen, 1 Encaps, 2 Decaps,
+ * batched or not) on `count` instances of set pid holds at most when made on a freshly
+ * trimmed context with the context's tuning, host or device buffers alike: the admission
+ * figure of a server that bounds device memory.  0 for invalid arguments. */
+size_t lwe_ctx_call_bytes(lwe_ctx* ctx, int pid, int op, size_t count);
 /* The context's own HIP stream (a hipStream_t; owned by the context, valid until
  * lwe_ctx_destroy).  Calls given a NULL stream run on it and return once it has finished;
  * a caller may also pass it explicitly to run asynchronously, so that each context's work
@@ -128,6 +145,16 @@ int lwe_encaps(lwe_ctx* ctx, int pid, const uint8_t* pk, const uint8_t* mu, uint
 int lwe_decaps(lwe_ctx* ctx, int pid, const uint8_t* sk, const uint8_t* ct, uint8_t* ss,
                void* hip_stream);
 
+/* ---- randomised: seeds and messages drawn from the operating system (getrandom(2)) ----
+ * KeyGen draws seedA, seedSK (16 bytes each) and z (32 bytes) per instance (Alg. 1 takes a
+ * fresh seed); Encaps draws the message mu (Alg. 4 starts by sampling mu uniformly).  The
+ * outputs are then those of lwe_keygen_batch / lwe_encaps_batch for the drawn inputs; the
+ * host copies of the drawn bytes are overwritten before the call returns.  count == 0 is a
+ * no-op; 1 <= count <= 65535.  LWE_EDEVICE if the random source fails. */
+int lwe_keygen_rand(lwe_ctx* ctx, int pid, size_t count, uint8_t* pk, uint8_t* sk, void* hip_stream);
+int lwe_encaps_rand(lwe_ctx* ctx, int pid, size_t count, const uint8_t* pk, uint8_t* ct, uint8_t* ss,
+                    void* hip_stream);
+
 /* ---- batched variants: `count` independent instances, arrays are [count][bytes] ----
  * Each instance's output is identical to what the single-instance call returns for the
  * same inputs.  encaps/decaps batches share one pk / one sk; keygen batches take count
@@ -153,6 +180,29 @@ int lwe_test_keystream(lwe_ctx* ctx, const uint8_t* key, uint32_t domain, uint64
  * as int16. */
 int lwe_test_sample(lwe_ctx* ctx, int pid, const uint8_t* key, uint32_t domain, uint64_t word0,
                     size_t count, int16_t* out, void* hip_stream);
+/* The batched sampler kernel of KeyGen (mode 0: S^T from domain 1, E^T from domain 2) or of
+ * Encrypt (mode 1: S' from domain 1, E' from domain 2, E'' from domain 3), Alg. 1-2, for
+ * count instances whose AES-128 keys are keys[count][16] (seedSK or coins).  Outputs, with
+ * ldx = n rounded up to a multiple of 64:
+ *   X_out  the int8 operand matrix of segment 0 as the products read it: layout 0 is
+ *          row-major [count*8][ldx]; layout 1 is MFMA fragment order over
+ *          ceil(count*8/16)*16 rows (16-row groups, then 64-column steps, then 64 lanes of 16
+ *          bytes; lane = row % 16 + 16 * (col % 64 / 16)); columns n .. ldx-1 are zero, and
+ *          bytes of rows past count*8 are left as 0x5a;
+ *   E_out  [count*8][n] int8 (segment 1);
+ *   E2_out [count][64] int8 (segment 2), mode 1 only (NULL in mode 0);
+ *   X16_out optional in mode 0 (NULL in mode 1): [count][8*n] int16, segment 0 as stored in sk. */
+int lwe_test_sample_batch(lwe_ctx* ctx, int pid, size_t count, int mode, int layout, const uint8_t* keys,
+                          int8_t* X_out, int8_t* E_out, int8_t* E2_out, uint8_t* X16_out, void* hip_stream);
+/* The encryption product with injected operands (Alg. 2 without the sampler): for count
+ * instances, B' = S A + E mod q and V = S B + E2 + encode(mu) mod q, where A comes from seedA
+ * (regenerated inside the product kernel the batch size selects), B = (B^T)^T with
+ * Bt = 8 x n uint16, S and E are [count*8][n] int8, E2 is [count][64] int8 and mu is
+ * [count][mu_bytes]; ct receives [count][ct_bytes] records (B' then V).  With S = unit rows and
+ * E = 0, B' row r is row r's selected row of A. */
+int lwe_test_product(lwe_ctx* ctx, int pid, size_t count, const uint8_t* seedA, const uint8_t* Bt,
+                     const int8_t* S, const int8_t* E, const int8_t* E2, const uint8_t* mu, uint8_t* ct,
+                     void* hip_stream);
 /* PKE encryption with explicit coins (no hashing): ct = Encrypt(pk, mu; coins). */
 int lwe_test_encrypt(lwe_ctx* ctx, int pid, size_t count, const uint8_t* pk,
                      const uint8_t* coins /* [count][16] */, const uint8_t* mu, uint8_t* ct,

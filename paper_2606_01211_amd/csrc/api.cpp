@@ -1,6 +1,8 @@
 // Host side of liblwe_hip: contexts, device working memory, staging of host buffers,
 // launch planning and the C ABI entry points declared in include/lwe.h.
+#include <errno.h>
 #include <string.h>
+#include <sys/random.h>
 
 #include <algorithm>
 #include <map>
@@ -16,6 +18,8 @@ namespace {
 
 // batch sizes map to grid.y of the sampling and keygen kernels
 constexpr size_t LWE_MAX_BATCH = 65535;
+// the AES T-table every context keeps on its device
+constexpr size_t T0_BYTES = 1024;
 
 enum BufId {
   B_SEEDA, B_SEEDSK, B_Z, B_RKA, B_RK, B_X, B_E, B_E2, B_COINS, B_KP, B_HCT, B_FLAGS, B_MU2,
@@ -25,6 +29,7 @@ enum BufId {
 struct Buf {
   void* p = nullptr;
   size_t cap = 0;
+  bool async = false;  // allocated with hipMallocAsync (freed with hipFreeAsync)
 };
 
 }  // namespace
@@ -38,8 +43,15 @@ struct lwe_ctx {
   bool use_side = true;
   int hash_lanes = 2;  // lanes per record of the batched SHA3 kernel (2 or 1)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  size_t budget = 0;  // 0 = unlimited
-  size_t held = 0;
+  // Calls on one context reuse its buffers.  Every call records ev_done on its stream when it
+  // has queued its work; a call on a different stream first waits for that event, so the
+  // context's calls execute in the order they were made whatever streams they are given.
+  hipEvent_t ev_done = nullptr;
+  hipStream_t last = nullptr;  // stream of the previous call (null before the first)
+  hipStream_t cur = nullptr;   // stream of the call in progress: orders buffer growth
+  bool async_alloc = false;    // the device supports stream-ordered allocation
+  size_t budget = 0;  // 0 = unlimited; bounds held
+  size_t held = 0;    // device bytes held: the growable buffers plus the AES table (T0_BYTES)
   uint32_t* d_T0 = nullptr;
   Buf bufs[B_COUNT];
   // cache of the last public key hashed on the host
@@ -106,18 +118,26 @@ int ensure(lwe_ctx* c, BufId id, size_t bytes, void** out) {
       if (c->held - b.cap + want > c->budget) return LWE_ENOMEM;
     }
     if (b.p) {
-      // the old buffer may still be read by queued work
-      if (hipDeviceSynchronize() != hipSuccess) return LWE_EDEVICE;
-      (void)hipFree(b.p);
+      // The old buffer may still be read by queued work of this context.  All of it is
+      // ordered before the current call's stream (CallScope), so it is freed in that stream's
+      // order; without stream-ordered allocation the device is drained first.
+      if (b.async && c->cur) {
+        if (hipFreeAsync(b.p, c->cur) != hipSuccess) return LWE_EDEVICE;
+      } else {
+        if (hipDeviceSynchronize() != hipSuccess) return LWE_EDEVICE;
+        (void)hipFree(b.p);
+      }
       c->held -= b.cap;
       b.p = nullptr;
       b.cap = 0;
     }
-    if (hipMalloc(&b.p, want) != hipSuccess) {
+    const bool async = c->async_alloc && c->cur;
+    if ((async ? hipMallocAsync(&b.p, want, c->cur) : hipMalloc(&b.p, want)) != hipSuccess) {
       (void)hipGetLastError();
       b.p = nullptr;
       return LWE_ENOMEM;
     }
+    b.async = async;
     b.cap = want;
     c->held += want;
   }
@@ -207,6 +227,27 @@ int finish_out(const OutStage& o, hipStream_t s) {
 
 hipStream_t pick_stream(lwe_ctx* c, void* user) { return user ? (hipStream_t)user : c->own; }
 
+// Brackets one entry point: orders it after the context's previous call when that call used
+// another stream, and marks the end of its work on its own stream for the next call.
+struct CallScope {
+  lwe_ctx* c;
+  hipStream_t s;
+  hipStream_t outer;
+  int status = LWE_OK;
+  CallScope(lwe_ctx* c_, hipStream_t s_) : c(c_), s(s_), outer(c_->cur) {
+    if (c->last && c->last != s && hipStreamWaitEvent(s, c->ev_done, 0) != hipSuccess) status = LWE_EDEVICE;
+    c->cur = s;
+  }
+  ~CallScope() {
+    if (hipEventRecord(c->ev_done, s) == hipSuccess) c->last = s;
+    c->cur = outer;
+  }
+};
+
+#define CALL_SCOPE(c, s)                 \
+  CallScope call_scope_(c, s);           \
+  LWE_CHECK(call_scope_.status)
+
 hipEvent_t prof_event(lwe_ctx* c) {
   if (!c->prof_pool.empty()) {
     hipEvent_t e = c->prof_pool.back();
@@ -288,20 +329,21 @@ bool use_host_hash(lwe_ctx* c, int pid, size_t count) {
 // The strip product (large row counts) reads S' in fragment order; the streaming one row-major.
 bool uses_strip(int M, bool trans, bool per_inst_A) { return !trans && !per_inst_A && M >= 256; }
 
-int run_product(lwe_ctx* c, int pid, const Params& p, ProdArgs a, bool trans, hipStream_t s) {
-  // a: operands, epilogue fields, M and ncols are filled in by the caller
+// Launch shape of one product.  plan_product fills the tiling fields of ProdArgs (K chunks,
+// column and row tiles); exec_product launches it.  A contraction split into K chunks needs a
+// zeroed int32 accumulator of acc_bytes, given in a.acc32 before exec_product.
+struct ProdPlan {
+  bool strip = false;
+  int CG = 1, RG = 1, W = 1, KS = 1, unr = 3;
+  size_t acc_bytes = 0;
+};
+
+ProdPlan plan_product(lwe_ctx* c, int pid, const Params& p, ProdArgs& a, bool trans) {
+  ProdPlan pl;
   const int ksteps = (p.n + 63) / 64;
   const lwe_tuning& tu = tuning_of(c, pid);
-  const bool strip = uses_strip(a.M, trans, a.per_inst_A != 0);
-  // Unfused variant: expand A once into device memory and let the product read it (one A per
-  // call, so not for key-generation batches, where every instance has its own A).
-  if (tu.a_source == 1 && (!a.per_inst_A || a.M == 8)) {
-    uint16_t* Am;
-    LWE_CHECK(ensure_t(c, B_AMAT, (size_t)p.n * p.n * 2, &Am));
-    KLAUNCH("expand_A", s, launch_expand_A(p, a.rkA, a.T0, 0, (uint32_t)p.n, Am, s));
-    a.Amat = Am;
-  }
-  if (!strip) {
+  pl.strip = uses_strip(a.M, trans, a.per_inst_A != 0);
+  if (!pl.strip) {
     int RG = 1;
     if (!a.per_inst_A) RG = a.M <= 16 ? 1 : (a.M <= 32 ? 2 : 4);
     const int CG = 1;
@@ -314,12 +356,10 @@ int run_product(lwe_ctx* c, int pid, const Params& p, ProdArgs a, bool trans, hi
     a.n_kc = (ksteps + W * KS - 1) / (W * KS);
     W = (ksteps + a.n_kc * KS - 1) / (a.n_kc * KS);
     a.kc_len = W * KS * 64;
-    if (a.n_kc > 1) {
-      a.acc_ld = a.ncols;
-      LWE_CHECK(ensure_t(c, B_ACC, (size_t)a.M * a.acc_ld * 4, &a.acc32));
-      KLAUNCH("fill", s, launch_fill_u32((uint32_t*)a.acc32, (size_t)a.M * a.acc_ld, 0, s));
-    }
-    KLAUNCH("prod_stream", s, launch_product_stream(a, CG, RG, W, trans, a.n_mt, KS, s));
+    pl.CG = CG;
+    pl.RG = RG;
+    pl.W = W;
+    pl.KS = KS;
   } else {
     // Default tile: the widest strip of A that fits LDS over the whole contraction (fewer
     // re-reads of the S' stack), and one row chunk per XCD so that all workgroups of an XCD
@@ -352,17 +392,45 @@ int run_product(lwe_ctx* c, int pid, const Params& p, ProdArgs a, bool trans, hi
     mch = std::min(mch, m_units);
     a.m_tile = ((m_units + mch - 1) / mch) * unit;
     a.n_mt = (a.M + a.m_tile - 1) / a.m_tile;
-    if (a.n_kc > 1) {
-      a.acc_ld = a.ncols;
-      LWE_CHECK(ensure_t(c, B_ACC, (size_t)a.M * a.acc_ld * 4, &a.acc32));
-      KLAUNCH("fill", s, launch_fill_u32((uint32_t*)a.acc32, (size_t)a.M * a.acc_ld, 0, s));
-    }
+    pl.CG = CG;
+    pl.RG = RG;
+    pl.unr = unr;
+  }
+  if (a.n_kc > 1) {
+    a.acc_ld = a.ncols;
+    pl.acc_bytes = (size_t)a.M * a.acc_ld * 4;
+  }
+  return pl;
+}
+
+int exec_product(lwe_ctx* c, const ProdPlan& pl, const ProdArgs& a, bool trans, hipStream_t s) {
+  if (a.n_kc > 1) KLAUNCH("fill", s, launch_fill_u32((uint32_t*)a.acc32, (size_t)a.M * a.acc_ld, 0, s));
+  if (!pl.strip) {
+    KLAUNCH("prod_stream", s, launch_product_stream(a, pl.CG, pl.RG, pl.W, trans, a.n_mt, pl.KS, s));
+  } else {
     // timed under separate names: the compare launch of a decapsulation shares the GPU with its
     // concurrent hash
-    KLAUNCH(a.mode == PM_COMPARE ? "prod_strip_cmp" : "prod_strip", s, launch_product_strip(a, CG, RG, unr, s));
+    KLAUNCH(a.mode == PM_COMPARE ? "prod_strip_cmp" : "prod_strip", s,
+            launch_product_strip(a, pl.CG, pl.RG, pl.unr, s));
   }
   if (a.n_kc > 1) KLAUNCH("finalize", s, launch_finalize(a, s));
   return LWE_OK;
+}
+
+int run_product(lwe_ctx* c, int pid, const Params& p, ProdArgs a, bool trans, hipStream_t s) {
+  // a: operands, epilogue fields, M and ncols are filled in by the caller
+  const lwe_tuning& tu = tuning_of(c, pid);
+  // Unfused variant: expand A once into device memory and let the product read it (one A per
+  // call, so not for key-generation batches, where every instance has its own A).
+  if (tu.a_source == 1 && (!a.per_inst_A || a.M == 8)) {
+    uint16_t* Am;
+    LWE_CHECK(ensure_t(c, B_AMAT, (size_t)p.n * p.n * 2, &Am));
+    KLAUNCH("expand_A", s, launch_expand_A(p, a.rkA, a.T0, 0, (uint32_t)p.n, Am, s));
+    a.Amat = Am;
+  }
+  const ProdPlan pl = plan_product(c, pid, p, a, trans);
+  if (pl.acc_bytes) LWE_CHECK(ensure_t(c, B_ACC, pl.acc_bytes, &a.acc32));
+  return exec_product(c, pl, a, trans, s);
 }
 
 // ------------------------------------------------------------------------------------
@@ -462,6 +530,7 @@ const char* lwe_strerror(int status) {
 int lwe_ctx_create(lwe_ctx** out, int device, size_t hbm_budget_bytes) {
   if (!out) return LWE_EINVAL;
   *out = nullptr;
+  if (hbm_budget_bytes && hbm_budget_bytes < T0_BYTES) return LWE_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
     (void)hipGetLastError();
@@ -471,19 +540,25 @@ int lwe_ctx_create(lwe_ctx** out, int device, size_t hbm_budget_bytes) {
   lwe_ctx* c = new lwe_ctx();
   c->device = device;
   c->budget = hbm_budget_bytes;
+  c->held = T0_BYTES;
   memset(c->tuning, 0, sizeof(c->tuning));
   unsigned hc = std::thread::hardware_concurrency();
   c->host_threads = (int)std::max(1u, std::min(hc, 16u));
   if (hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
-      hipMalloc(&c->d_T0, 1024) != hipSuccess ||
-      hipMemcpy(c->d_T0, aes_T0(), 1024, hipMemcpyHostToDevice) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming) != hipSuccess ||
+      hipMalloc(&c->d_T0, T0_BYTES) != hipSuccess ||
+      hipMemcpy(c->d_T0, aes_T0(), T0_BYTES, hipMemcpyHostToDevice) != hipSuccess ||
       init_kernels() != hipSuccess) {
     (void)hipGetLastError();
     lwe_ctx_destroy(c);
     return LWE_EDEVICE;
   }
+  int pools = 0;
+  c->async_alloc = hipDeviceGetAttribute(&pools, hipDeviceAttributeMemoryPoolsSupported, device) == hipSuccess &&
+                   pools != 0;
+  (void)hipGetLastError();
   *out = c;
   return LWE_OK;
 }
@@ -492,8 +567,14 @@ void lwe_ctx_destroy(lwe_ctx* c) {
   if (!c) return;
   DevGuard g(c->device);
   (void)hipDeviceSynchronize();
-  for (auto& b : c->bufs)
-    if (b.p) (void)hipFree(b.p);
+  for (auto& b : c->bufs) {
+    if (!b.p) continue;
+    if (b.async)
+      (void)hipFreeAsync(b.p, c->own);
+    else
+      (void)hipFree(b.p);
+  }
+  if (c->own) (void)hipStreamSynchronize(c->own);
   if (c->d_T0) (void)hipFree(c->d_T0);
   for (auto& r : c->prof_pending) {
     (void)hipEventDestroy(r.a);
@@ -502,12 +583,77 @@ void lwe_ctx_destroy(lwe_ctx* c) {
   for (auto e : c->prof_pool) (void)hipEventDestroy(e);
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  if (c->ev_done) (void)hipEventDestroy(c->ev_done);
   if (c->side) (void)hipStreamDestroy(c->side);
   if (c->own) (void)hipStreamDestroy(c->own);
   delete c;
 }
 
-size_t lwe_ctx_device_bytes(const lwe_ctx* c) { return c ? c->held + 1024 : 0; }
+size_t lwe_ctx_device_bytes(const lwe_ctx* c) { return c ? c->held : 0; }
+
+int lwe_ctx_set_budget(lwe_ctx* c, size_t hbm_budget_bytes) {
+  if (!c || (hbm_budget_bytes && hbm_budget_bytes < T0_BYTES)) return LWE_EINVAL;
+  c->budget = hbm_budget_bytes;
+  return LWE_OK;
+}
+
+int lwe_ctx_trim(lwe_ctx* c) {
+  if (!c) return LWE_EINVAL;
+  DevGuard g(c->device);
+  // every queued use of the buffers is ordered before the end of the last call's stream
+  hipStream_t s = c->last ? c->last : c->own;
+  for (auto& b : c->bufs) {
+    if (!b.p) continue;
+    if (b.async) {
+      HIP_CHECK(hipFreeAsync(b.p, s));
+    } else {
+      HIP_CHECK(hipStreamSynchronize(s));
+      HIP_CHECK(hipFree(b.p));
+    }
+    c->held -= b.cap;
+    b.p = nullptr;
+    b.cap = 0;
+    b.async = false;
+  }
+  return LWE_OK;
+}
+
+size_t lwe_ctx_call_bytes(lwe_ctx* c, int pid, int op, size_t count) {
+  const Params* p = get_params(pid);
+  if (!c || !p || op < 0 || op > 2 || count == 0 || count > LWE_MAX_BATCH) return 0;
+  auto r = [](size_t b) { return ((b ? b : 16) + 255) & ~(size_t)255; };  // as ensure() rounds
+  const size_t n = (size_t)p->n, ldx = (size_t)p->ldx, mb = p->mu_bytes;
+  const lwe_tuning& tu = tuning_of(c, pid);
+  // product split-K accumulator and, for the unfused variant, the expanded A
+  auto product = [&](int M, int ncols, bool trans, bool per_inst_A) {
+    ProdArgs a;
+    memset(&a, 0, sizeof(a));
+    a.M = M;
+    a.ncols = ncols;
+    a.per_inst_A = per_inst_A ? 1 : 0;
+    size_t b = 0;
+    if (tu.a_source == 1 && (!per_inst_A || M == 8)) b += r(n * n * 2);
+    const ProdPlan pl = plan_product(c, pid, *p, a, trans);
+    if (pl.acc_bytes) b += r(pl.acc_bytes);
+    return b;
+  };
+  const size_t M = count * 8;
+  // encrypt_core: S' (whole 16-row groups), E', E'', round keys of seedA
+  const size_t enc = r((M + 15) / 16 * 16 * ldx) + r(M * n) + r(count * 64) + r(44 * 4) +
+                     product((int)M, (int)(n + 8), false, false);
+  size_t b = 0;
+  if (op == 0) {
+    b = r(count * 16) * 2 + r(count * 32) + r(count * p->pk_bytes) + r(count * p->sk_bytes) + r(count * 44 * 4) * 2 +
+        r(M * ldx) + r(M * n) + product((int)M, (int)n, true, true) + r(count * 32);
+  } else if (op == 1) {
+    b = r(p->pk_bytes) + r(count * mb) + r(count * p->ct_bytes) + r(count * 32) + r(count * 16) + r(count * 32) +
+        r(count * 44 * 4) + r(32) + enc + r(count * 32);
+  } else {
+    b = r(p->sk_bytes) + r(count * p->ct_bytes) + r(count * 32) + r(count * mb) + r(count * 16) + r(count * 32) +
+        r(count * 44 * 4) + r(count * 4) + enc + r(count * 32);
+  }
+  return b + T0_BYTES;
+}
 void* lwe_ctx_stream(lwe_ctx* c) { return c ? (void*)c->own : nullptr; }
 
 int lwe_ctx_set_hash_lanes(lwe_ctx* c, int lanes) {
@@ -624,6 +770,7 @@ int lwe_keygen_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* seedA, co
   const Params& p = *pp;
   DevGuard g(c->device);
   hipStream_t s = pick_stream(c, stream);
+  CALL_SCOPE(c, s);
   const int n = p.n;
   const uint8_t *dA, *dS, *dZ;
   LWE_CHECK(stage_in(c, B_SEEDA, seedA, count * 16, s, &dA));
@@ -720,6 +867,7 @@ int lwe_encaps_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* pk, const
   const Params& p = *pp;
   DevGuard g(c->device);
   hipStream_t s = pick_stream(c, stream);
+  CALL_SCOPE(c, s);
   const size_t mb = p.mu_bytes;
   // H(pk) on the host (cached per public key); with host hashing the messages come back in the
   // same wait
@@ -809,6 +957,7 @@ int lwe_decaps_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* sk, const
   const Params& p = *pp;
   DevGuard g(c->device);
   hipStream_t s = pick_stream(c, stream);
+  CALL_SCOPE(c, s);
   const int n = p.n;
   const size_t mb = p.mu_bytes;
   const size_t off_pk = (size_t)16 * n, off_pkh = off_pk + p.pk_bytes, off_z = off_pkh + 32;
@@ -935,6 +1084,7 @@ int lwe_test_expand_A(lwe_ctx* c, int pid, const uint8_t* seedA, uint32_t col0, 
   if ((uint64_t)col0 + ncols > (uint64_t)p.n) return LWE_EINVAL;
   DevGuard g(c->device);
   hipStream_t s = pick_stream(c, stream);
+  CALL_SCOPE(c, s);
   const uint8_t* dA;
   LWE_CHECK(stage_in(c, B_SEEDA, seedA, 16, s, &dA));
   uint32_t* rk;
@@ -953,6 +1103,7 @@ int lwe_test_keystream(lwe_ctx* c, const uint8_t* key, uint32_t domain, uint64_t
   if (!c || !key || !out) return LWE_EINVAL;
   DevGuard g(c->device);
   hipStream_t s = pick_stream(c, stream);
+  CALL_SCOPE(c, s);
   const uint8_t* dk;
   LWE_CHECK(stage_in(c, B_SEEDA, key, 16, s, &dk));
   uint32_t* rk;
@@ -973,6 +1124,7 @@ int lwe_test_sample(lwe_ctx* c, int pid, const uint8_t* key, uint32_t domain, ui
   LWE_CHECK(check_pid(pid, &pp));
   DevGuard g(c->device);
   hipStream_t s = pick_stream(c, stream);
+  CALL_SCOPE(c, s);
   const uint8_t* dk;
   LWE_CHECK(stage_in(c, B_SEEDA, key, 16, s, &dk));
   uint32_t* rk;
@@ -995,6 +1147,7 @@ int lwe_test_encrypt(lwe_ctx* c, int pid, size_t count, const uint8_t* pk, const
   const Params& p = *pp;
   DevGuard g(c->device);
   hipStream_t s = pick_stream(c, stream);
+  CALL_SCOPE(c, s);
   const uint8_t *dpk, *dco, *dmu;
   LWE_CHECK(stage_in(c, B_PK, pk, p.pk_bytes, s, &dpk));
   LWE_CHECK(stage_in(c, B_SEEDSK, coins, count * 16, s, &dco));
@@ -1019,6 +1172,7 @@ int lwe_test_decrypt(lwe_ctx* c, int pid, size_t count, const uint8_t* sk, const
   const Params& p = *pp;
   DevGuard g(c->device);
   hipStream_t s = pick_stream(c, stream);
+  CALL_SCOPE(c, s);
   const uint8_t *dsk, *dct;
   LWE_CHECK(stage_in(c, B_SK, sk, p.sk_bytes, s, &dsk));
   LWE_CHECK(stage_in(c, B_CT, ct, count * p.ct_bytes, s, &dct));
@@ -1045,6 +1199,7 @@ int lwe_test_sha3(lwe_ctx* c, size_t count, size_t len, const uint8_t* in, uint8
   if (count == 0) return LWE_OK;
   DevGuard g(c->device);
   hipStream_t s = pick_stream(c, stream);
+  CALL_SCOPE(c, s);
   const uint8_t* din;
   LWE_CHECK(stage_in(c, B_CT, in, count * len, s, &din));
   OutStage o;
@@ -1053,6 +1208,166 @@ int lwe_test_sha3(lwe_ctx* c, size_t count, size_t len, const uint8_t* in, uint8
   LWE_CHECK(finish_out(o, s));
   HIP_CHECK(hipStreamSynchronize(s));
   return LWE_OK;
+}
+
+
+int lwe_test_sample_batch(lwe_ctx* c, int pid, size_t count, int mode, int layout, const uint8_t* keys,
+                          int8_t* X_out, int8_t* E_out, int8_t* E2_out, uint8_t* X16_out, void* stream) {
+  const Params* pp;
+  if (!c || !keys || !X_out || !E_out || count == 0 || count > LWE_MAX_BATCH) return LWE_EINVAL;
+  if ((mode != 0 && mode != 1) || (layout != 0 && layout != 1)) return LWE_EINVAL;
+  if ((mode == 1) != (E2_out != nullptr) || (mode == 1 && X16_out)) return LWE_EINVAL;
+  LWE_CHECK(check_pid(pid, &pp));
+  const Params& p = *pp;
+  DevGuard g(c->device);
+  hipStream_t s = pick_stream(c, stream);
+  CALL_SCOPE(c, s);
+  const int n = p.n;
+  const uint8_t* dk;
+  LWE_CHECK(stage_in(c, B_SEEDSK, keys, count * 16, s, &dk));
+  uint32_t* rk;
+  LWE_CHECK(ensure_t(c, B_RK, count * 44 * 4, &rk));
+  KLAUNCH("expand_keys", s, launch_expand_keys(dk, 16, (int)count, c->d_T0, rk, s));
+  const size_t x_bytes = (layout ? (count * 8 + 15) / 16 * 16 : count * 8) * (size_t)p.ldx;
+  OutStage ox, oe, oe2, o16;
+  LWE_CHECK(stage_out(c, B_X, X_out, x_bytes, ox));
+  LWE_CHECK(stage_out(c, B_E, E_out, count * 8 * (size_t)n, oe));
+  if (E2_out) LWE_CHECK(stage_out(c, B_E2, E2_out, count * 64, oe2));
+  if (X16_out) LWE_CHECK(stage_out(c, B_SK, X16_out, count * 16 * (size_t)n, o16));
+  // bytes the sampler does not own (unwritten rows of the last fragment group) stay 0x5a
+  KLAUNCH("fill", s, launch_fill_u32((uint32_t*)ox.dev, x_bytes / 4, 0x5a5a5a5au, s));
+  SampleArgs sa;
+  memset(&sa, 0, sizeof(sa));
+  sa.rk = rk;
+  sa.T0 = c->d_T0;
+  sa.n = n;
+  sa.K = p.K;
+  sa.ldx = p.ldx;
+  sa.nseg = mode ? 3 : 2;
+  for (int k = 0; k < MAX_K; ++k) sa.T2[k] = (uint32_t)p.T[k] * 0x10001u;
+  sa.X = (int8_t*)ox.dev;
+  sa.x_frag = layout;
+  sa.X16 = X16_out ? o16.dev : nullptr;
+  sa.x16_stride = 16 * (size_t)n;
+  sa.E = (int8_t*)oe.dev;
+  sa.E2 = E2_out ? (int8_t*)oe2.dev : nullptr;
+  KLAUNCH("sample", s, launch_sample(sa, (int)count, s));
+  LWE_CHECK(finish_out(ox, s));
+  LWE_CHECK(finish_out(oe, s));
+  if (E2_out) LWE_CHECK(finish_out(oe2, s));
+  if (X16_out) LWE_CHECK(finish_out(o16, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  return LWE_OK;
+}
+
+int lwe_test_product(lwe_ctx* c, int pid, size_t count, const uint8_t* seedA, const uint8_t* Bt, const int8_t* S,
+                     const int8_t* E, const int8_t* E2, const uint8_t* mu, uint8_t* ct, void* stream) {
+  const Params* pp;
+  if (!c || !seedA || !Bt || !S || !E || !E2 || !mu || !ct || count == 0 || count > LWE_MAX_BATCH)
+    return LWE_EINVAL;
+  LWE_CHECK(check_pid(pid, &pp));
+  const Params& p = *pp;
+  DevGuard g(c->device);
+  hipStream_t s = pick_stream(c, stream);
+  CALL_SCOPE(c, s);
+  const int n = p.n;
+  const size_t rows = count * 8;
+  const uint8_t *dA, *dBt, *dS, *dE, *dE2, *dmu;
+  LWE_CHECK(stage_in(c, B_SEEDA, seedA, 16, s, &dA));
+  LWE_CHECK(stage_in(c, B_PK, Bt, 16 * (size_t)n, s, &dBt));
+  LWE_CHECK(stage_in(c, B_TEST, S, rows * n, s, &dS));
+  LWE_CHECK(stage_in(c, B_E, E, rows * n, s, &dE));
+  LWE_CHECK(stage_in(c, B_E2, E2, count * 64, s, &dE2));
+  LWE_CHECK(stage_in(c, B_MU, mu, count * p.mu_bytes, s, &dmu));
+  OutStage o;
+  LWE_CHECK(stage_out(c, B_CT, ct, count * p.ct_bytes, o));
+  uint32_t* rkA;
+  LWE_CHECK(ensure_t(c, B_RKA, 44 * 4, &rkA));
+  KLAUNCH("expand_keys", s, launch_expand_keys(dA, 16, 1, c->d_T0, rkA, s));
+  // S' into the operand layout of the product this batch size selects
+  const bool frag = uses_strip((int)rows, false, false);
+  int8_t* X;
+  LWE_CHECK(ensure_t(c, B_X, (rows + 15) / 16 * 16 * (size_t)p.ldx, &X));
+  HIP_CHECK(launch_pack_x((const int8_t*)dS, (int)rows, n, p.ldx, frag ? 1 : 0, X, s));
+  ProdArgs a;
+  memset(&a, 0, sizeof(a));
+  a.rkA = rkA;
+  a.T0 = c->d_T0;
+  a.X = X;
+  a.ldx = p.ldx;
+  a.M = (int)rows;
+  a.n = n;
+  a.logq = p.logq;
+  a.B = p.B;
+  a.ncols = n + 8;
+  a.Bt = dBt;
+  a.mode = PM_ENCRYPT;
+  a.E = (const int8_t*)dE;
+  a.E2 = (const int8_t*)dE2;
+  a.mu = dmu;
+  a.mu_stride = p.mu_bytes;
+  a.out = o.dev;
+  a.out_stride = p.ct_bytes;
+  LWE_CHECK(run_product(c, pid, p, a, false, s));
+  LWE_CHECK(finish_out(o, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  return LWE_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// Fills buf with bytes from the operating system's random source (getrandom(2)).
+int os_random(uint8_t* buf, size_t len) {
+  size_t got = 0;
+  while (got < len) {
+    const ssize_t r = getrandom(buf + got, len - got, 0);
+    if (r < 0) {
+      if (errno == EINTR) continue;
+      return LWE_EDEVICE;
+    }
+    got += (size_t)r;
+  }
+  return LWE_OK;
+}
+
+void wipe(std::vector<uint8_t>& v) {
+  volatile uint8_t* p = v.data();
+  for (size_t i = 0; i < v.size(); ++i) p[i] = 0;
+}
+}  // namespace
+
+extern "C" {
+
+int lwe_keygen_rand(lwe_ctx* c, int pid, size_t count, uint8_t* pk, uint8_t* sk, void* stream) {
+  const Params* pp;
+  if (!c) return LWE_EINVAL;
+  LWE_CHECK(check_pid(pid, &pp));
+  if (count == 0) return LWE_OK;
+  if (!pk || !sk || count > LWE_MAX_BATCH) return LWE_EINVAL;
+  std::vector<uint8_t> seeds(count * 64);  // seedA (16) | seedSK (16) | z (32) blocks
+  int st = os_random(seeds.data(), seeds.size());
+  if (st == LWE_OK)
+    st = lwe_keygen_batch(c, pid, count, seeds.data(), seeds.data() + count * 16, seeds.data() + count * 32, pk, sk,
+                          stream);
+  // the staged seeds must have left host memory before it is wiped
+  if (st == LWE_OK && stream && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) st = LWE_EDEVICE;
+  wipe(seeds);
+  return st;
+}
+
+int lwe_encaps_rand(lwe_ctx* c, int pid, size_t count, const uint8_t* pk, uint8_t* ct, uint8_t* ss, void* stream) {
+  const Params* pp;
+  if (!c) return LWE_EINVAL;
+  LWE_CHECK(check_pid(pid, &pp));
+  if (count == 0) return LWE_OK;
+  if (!pk || !ct || !ss || count > LWE_MAX_BATCH) return LWE_EINVAL;
+  std::vector<uint8_t> mu(count * pp->mu_bytes);
+  int st = os_random(mu.data(), mu.size());
+  if (st == LWE_OK) st = lwe_encaps_batch(c, pid, count, pk, mu.data(), ct, ss, stream);
+  if (st == LWE_OK && stream && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) st = LWE_EDEVICE;
+  wipe(mu);
+  return st;
 }
 
 }  // extern "C"

@@ -409,6 +409,18 @@ __global__ void k_fill_u32(uint32_t* p, size_t count, uint32_t v) {
   for (; i < count; i += stride) p[i] = v;
 }
 
+// Copies a row-major [rows][n] int8 matrix into the layout the products read: row-major with
+// row stride ldx, or MFMA fragment order (frag_offset); columns n .. ldx-1 become zero.  One
+// thread per destination byte of the `rows` rows.
+__global__ void k_pack_x(const int8_t* __restrict__ src, int rows, int n, int ldx, int frag,
+                         int8_t* __restrict__ dst) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (size_t)rows * ldx) return;
+  const int row = (int)(t / ldx), k = (int)(t - (size_t)row * ldx);
+  const int8_t v = k < n ? src[(size_t)row * n + k] : (int8_t)0;
+  dst[frag ? frag_offset(row, k, ldx >> 6) : (size_t)row * ldx + k] = v;
+}
+
 // FIPS-197 key expansion, one key per thread; the S-box comes from byte 1 of T0.
 __global__ void k_expand_keys(const uint8_t* __restrict__ keys, size_t key_stride, int count,
                               const uint32_t* __restrict__ T0, uint32_t* __restrict__ rk_out) {
@@ -1762,6 +1774,13 @@ hipError_t launch_expand_A(const Params& p, const uint32_t* rk, const uint32_t* 
   const unsigned grid = (unsigned)std::min<size_t>((units + EXPAND_WAVES - 1) / EXPAND_WAVES, 2 * (size_t)g_num_cus);
   hipLaunchKernelGGL(k_expand_A, dim3(grid), dim3(64 * EXPAND_WAVES), 0, s, qmask2, rk, T0, (uint64_t)col0 * bpc,
                      nblocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_x(const int8_t* src, int rows, int n, int ldx, int frag, int8_t* dst, hipStream_t s) {
+  const size_t total = (size_t)rows * ldx;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pack_x, dim3(nblk(total, 256)), dim3(256), 0, s, src, rows, n, ldx, frag, dst);
   return hipGetLastError();
 }
 

@@ -100,6 +100,7 @@ hipError_t launch_sample_stream(const Params& p, const uint32_t* rk, const uint3
                                 uint32_t domain, uint64_t word0, size_t count, int16_t* out,
                                 hipStream_t s);
 hipError_t launch_sample(const SampleArgs& a, int count, hipStream_t s);
+hipError_t launch_pack_x(const int8_t* src, int rows, int n, int ldx, int frag, int8_t* dst, hipStream_t s);
 hipError_t launch_product_stream(const ProdArgs& a, int cg, int rg, int waves, bool trans,
                                  int n_row_tiles, int ksteps_per_wave, hipStream_t s);
 hipError_t launch_product_strip(const ProdArgs& a, int cg, int rg, int unr, hipStream_t s);

@@ -23,13 +23,16 @@ LWE_OK, LWE_EINVAL, LWE_ENOMEM, LWE_EDEVICE, LWE_EUNSUPPORTED = 0, -1, -2, -3, -
 
 # every symbol include/lwe.h declares
 EXPORTS = [
-    "lwe_ctx_create", "lwe_ctx_destroy", "lwe_ctx_device_bytes", "lwe_ctx_stream",
+    "lwe_ctx_create", "lwe_ctx_destroy", "lwe_ctx_device_bytes", "lwe_ctx_set_budget", "lwe_ctx_trim",
+    "lwe_ctx_call_bytes", "lwe_ctx_stream",
     "lwe_ctx_set_side_stream", "lwe_ctx_set_hash_lanes", "lwe_strerror",
     "lwe_param_id", "lwe_param_register", "lwe_param_get", "lwe_pk_bytes", "lwe_sk_bytes",
     "lwe_ct_bytes", "lwe_mu_bytes", "lwe_cdf_table",
     "lwe_keygen", "lwe_encaps", "lwe_decaps",
+    "lwe_keygen_rand", "lwe_encaps_rand",
     "lwe_keygen_batch", "lwe_encaps_batch", "lwe_decaps_batch",
-    "lwe_test_expand_A", "lwe_test_keystream", "lwe_test_sample", "lwe_test_encrypt",
+    "lwe_test_expand_A", "lwe_test_keystream", "lwe_test_sample", "lwe_test_sample_batch",
+    "lwe_test_product", "lwe_test_encrypt",
     "lwe_test_decrypt", "lwe_test_sha3", "lwe_set_tuning", "lwe_get_tuning",
     "lwe_prof_enable", "lwe_prof_reset", "lwe_prof_read",
 ]
@@ -88,6 +91,9 @@ def lib() -> C.CDLL:
         "lwe_ctx_create": (i32, [C.POINTER(vp), i32, sz]),
         "lwe_ctx_destroy": (None, [vp]),
         "lwe_ctx_device_bytes": (sz, [vp]),
+        "lwe_ctx_set_budget": (i32, [vp, sz]),
+        "lwe_ctx_trim": (i32, [vp]),
+        "lwe_ctx_call_bytes": (sz, [vp, i32, i32, sz]),
         "lwe_ctx_stream": (vp, [vp]),
         "lwe_ctx_set_side_stream": (i32, [vp, i32]),
         "lwe_ctx_set_hash_lanes": (i32, [vp, i32]),
@@ -103,12 +109,16 @@ def lib() -> C.CDLL:
         "lwe_keygen": (i32, [vp, i32, vp, vp, vp, vp, vp, vp]),
         "lwe_encaps": (i32, [vp, i32, vp, vp, vp, vp, vp]),
         "lwe_decaps": (i32, [vp, i32, vp, vp, vp, vp]),
+        "lwe_keygen_rand": (i32, [vp, i32, sz, vp, vp, vp]),
+        "lwe_encaps_rand": (i32, [vp, i32, sz, vp, vp, vp, vp]),
         "lwe_keygen_batch": (i32, [vp, i32, sz, vp, vp, vp, vp, vp, vp]),
         "lwe_encaps_batch": (i32, [vp, i32, sz, vp, vp, vp, vp, vp]),
         "lwe_decaps_batch": (i32, [vp, i32, sz, vp, vp, vp, vp]),
         "lwe_test_expand_A": (i32, [vp, i32, vp, u32, u32, vp, vp]),
         "lwe_test_keystream": (i32, [vp, vp, u32, u64, sz, vp, vp]),
         "lwe_test_sample": (i32, [vp, i32, vp, u32, u64, sz, vp, vp]),
+        "lwe_test_sample_batch": (i32, [vp, i32, sz, i32, i32, vp, vp, vp, vp, vp, vp]),
+        "lwe_test_product": (i32, [vp, i32, sz, vp, vp, vp, vp, vp, vp, vp, vp]),
         "lwe_test_encrypt": (i32, [vp, i32, sz, vp, vp, vp, vp, vp]),
         "lwe_test_decrypt": (i32, [vp, i32, sz, vp, vp, vp, vp]),
         "lwe_test_sha3": (i32, [vp, sz, sz, vp, vp, vp]),
@@ -267,6 +277,22 @@ class Context:
     def device_bytes(self) -> int:
         return self._lib.lwe_ctx_device_bytes(self._h)
 
+    def set_budget(self, nbytes: int) -> None:
+        """Bound on device_bytes for later calls (0 = none); held memory is not released."""
+        _check(self._lib.lwe_ctx_set_budget(self._h, int(nbytes)), "lwe_ctx_set_budget")
+
+    def trim(self) -> None:
+        """Release the context's working buffers (ordered after its queued work)."""
+        _check(self._lib.lwe_ctx_trim(self._h), "lwe_ctx_trim")
+
+    def call_bytes(self, pid: int, op: int, count: int) -> int:
+        """Device bytes one call of op (0 KeyGen, 1 Encaps, 2 Decaps) on count instances holds
+        at most, starting from a trimmed context."""
+        b = self._lib.lwe_ctx_call_bytes(self._h, pid, int(op), int(count))
+        if b == 0:
+            raise LweError(LWE_EINVAL, "lwe_ctx_call_bytes")
+        return b
+
     @property
     def stream_handle(self) -> int:
         """The context's own HIP stream (an integer handle, e.g. for torch.cuda.ExternalStream)."""
@@ -336,6 +362,20 @@ class Context:
         _check(self._lib.lwe_decaps_batch(self._h, pid, count, *[x.ptr for x in a], st),
                "lwe_decaps_batch")
 
+    def keygen_rand(self, pid, count, pk, sk, stream=None):
+        """KeyGen with seeds drawn from the operating system's random source."""
+        p = params(pid)
+        a = [_Arg(pk, p.pk_bytes * count, True), _Arg(sk, p.sk_bytes * count, True)]
+        st = _stream_ptr(a, stream)
+        _check(self._lib.lwe_keygen_rand(self._h, pid, count, a[0].ptr, a[1].ptr, st), "lwe_keygen_rand")
+
+    def encaps_rand(self, pid, count, pk, ct, ss, stream=None):
+        """Encaps of messages drawn from the operating system's random source."""
+        p = params(pid)
+        a = [_Arg(pk, p.pk_bytes), _Arg(ct, p.ct_bytes * count, True), _Arg(ss, 32 * count, True)]
+        st = _stream_ptr(a, stream)
+        _check(self._lib.lwe_encaps_rand(self._h, pid, count, *[x.ptr for x in a], st), "lwe_encaps_rand")
+
     def keygen(self, pid, seedA, seedSK, z, pk, sk, stream=None):
         p = params(pid)
         a = [_Arg(seedA, 16), _Arg(seedSK, 16), _Arg(z, 32), _Arg(pk, p.pk_bytes, True),
@@ -372,6 +412,25 @@ class Context:
         a = [_Arg(key, 16), _Arg(out, 2 * count, True)]
         _check(self._lib.lwe_test_sample(self._h, pid, a[0].ptr, domain, word0, count, a[1].ptr,
                                          _stream_ptr(a, stream)), "lwe_test_sample")
+
+    def test_sample_batch(self, pid, count, mode, layout, keys, X, E, E2=None, X16=None, stream=None):
+        """The batched sampler kernel (mode 0 KeyGen, 1 Encrypt) into the operand layout
+        (0 row-major, 1 MFMA fragment order); see lwe_test_sample_batch."""
+        p = params(pid)
+        ldx = (p.n + 63) // 64 * 64
+        rows = (count * 8 + 15) // 16 * 16 if layout else count * 8
+        a = [_Arg(keys, 16 * count), _Arg(X, rows * ldx, True), _Arg(E, 8 * count * p.n, True),
+             _Arg(E2, 64 * count, True), _Arg(X16, 16 * p.n * count, True)]
+        _check(self._lib.lwe_test_sample_batch(self._h, pid, count, mode, layout, *[x.ptr for x in a],
+                                               _stream_ptr(a, stream)), "lwe_test_sample_batch")
+
+    def test_product(self, pid, count, seedA, Bt, S, E, E2, mu, ct, stream=None):
+        """The encryption product with injected S', E', E'' (see lwe_test_product)."""
+        p = params(pid)
+        a = [_Arg(seedA, 16), _Arg(Bt, 16 * p.n), _Arg(S, 8 * count * p.n), _Arg(E, 8 * count * p.n),
+             _Arg(E2, 64 * count), _Arg(mu, p.mu_bytes * count), _Arg(ct, p.ct_bytes * count, True)]
+        _check(self._lib.lwe_test_product(self._h, pid, count, *[x.ptr for x in a], _stream_ptr(a, stream)),
+               "lwe_test_product")
 
     def test_encrypt(self, pid, count, pk, coins, mu, ct, stream=None):
         p = params(pid)

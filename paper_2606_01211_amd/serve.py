@@ -72,7 +72,12 @@ def footprint_bytes(n: int, op: int, count: int) -> int:
 
 
 class Backend:
-    """What the scheduler needs from the device side (the real one is LibraryBackend)."""
+    """What the scheduler needs from the device side (the real one is LibraryBackend).
+
+    Memory: a lane holds held_bytes(lane) of device memory between groups; before a group the
+    server calls limit_lane(lane, cap) with the most the lane may hold until that group
+    completes, and may call trim(lane) on an idle lane to release what it holds.  A backend
+    without device memory of its own keeps the defaults (nothing held, no limits)."""
 
     def lanes(self) -> int:
         raise NotImplementedError
@@ -80,23 +85,45 @@ class Backend:
     def run(self, lane: int, op: int, n: int, key: int, payloads: List[Tuple]) -> List:
         raise NotImplementedError
 
+    def held_bytes(self, lane: int) -> int:
+        return 0
+
+    def limit_lane(self, lane: int, cap: int) -> None:
+        pass
+
+    def trim(self, lane: int) -> None:
+        pass
+
+    def call_bytes(self, n: int, op: int, count: int) -> Optional[int]:
+        """Device bytes one group needs starting from a trimmed lane (None: unknown)."""
+        return None
+
 
 class Server:
     """Continuous-batching scheduler.
 
     backend     executes one group on a lane and returns one result per request
-    hbm_budget  bytes of device working memory all in-flight groups may reserve
+    hbm_budget  bytes of device memory all lanes together may hold
     max_batch   largest group handed to one library call
     clock       time source (seconds); injectable for tests
+    footprint   bytes one group needs; default: the backend's call_bytes, else an estimate
+
+    Admission: every lane has a commitment, the device memory it holds when idle and, while
+    it runs a group, the cap the backend enforces for that group (what it held plus the
+    group's footprint, or the footprint alone after trimming the lane).  A group is dispatched
+    only when the commitments stay within hbm_budget, so the memory the lanes really hold
+    never exceeds it.
     """
 
     def __init__(self, backend: Backend, hbm_budget: int, max_batch: int = 4096,
                  clock: Callable[[], float] = time.perf_counter,
-                 footprint: Callable[[int, int, int], int] = footprint_bytes):
+                 footprint: Optional[Callable[[int, int, int], int]] = None):
         self.backend = backend
         self.budget = int(hbm_budget)
         self.max_batch = int(max_batch)
         self.clock = clock
+        if footprint is None:
+            footprint = footprint_bytes if backend.call_bytes(640, ENCAPS, 1) is None else backend.call_bytes
         self.footprint = footprint
         self._queues: Dict[Tuple[int, int, int], collections.deque] = {}
         # (arrival of the queue head, sequence, queue key) of every non-empty queue: the
@@ -105,11 +132,15 @@ class Server:
         self._seq = 0
         self._cv = threading.Condition()
         self._free_lanes = list(range(backend.lanes()))
-        self._reserved = 0
-        self.max_reserved = 0
+        self._commit = [int(backend.held_bytes(lane)) for lane in range(backend.lanes())]
+        self._reserved = sum(self._commit)
+        self.max_reserved = self._reserved
+        self.max_held = self._reserved  # largest total after a group completed (idle lanes' real bytes)
+        self.trims = 0
         self.max_in_flight_groups = 0
         self._in_flight = 0
         self._stop = False
+        self._paused = False
         self._pool = cf.ThreadPoolExecutor(max_workers=backend.lanes(), thread_name_prefix="lwe-lane")
         self._sched = threading.Thread(target=self._loop, name="lwe-scheduler", daemon=True)
         self.completed: List[Request] = []
@@ -140,9 +171,23 @@ class Server:
     def close(self) -> None:
         with self._cv:
             self._stop = True
+            self._paused = False
             self._cv.notify_all()
         self._sched.join()
         self._pool.shutdown(wait=True)
+        for lane in range(self.backend.lanes()):
+            self.backend.limit_lane(lane, 0)  # the lanes leave the server without a cap
+
+    def pause(self) -> None:
+        """Holds dispatching (requests keep queueing) until resume(): lets a caller submit a
+        burst that the scheduler then sees whole."""
+        with self._cv:
+            self._paused = True
+
+    def resume(self) -> None:
+        with self._cv:
+            self._paused = False
+            self._cv.notify_all()
 
     def __enter__(self):
         return self
@@ -151,8 +196,9 @@ class Server:
         self.close()
 
     # ---- scheduler ----
-    def _pick_group(self) -> Optional[Tuple[Tuple[int, int, int], List[Request], int]]:
-        """Oldest queue head first; as many of its requests as fit the free budget."""
+    def _pick_group(self, lane: int) -> Optional[Tuple[Tuple[int, int, int], List[Request], int, bool]]:
+        """Oldest queue head first; as many of its requests as fit the budget on idle lane
+        `lane`.  Returns (queue key, requests, cap for the lane, trim the lane first)."""
         while self._heads:
             arrival, seq, best = self._heads[0]
             q = self._queues.get(best)
@@ -163,25 +209,50 @@ class Server:
         else:
             return None
         op, n, key = best
-        free = self.budget - self._reserved
+        held = self._commit[lane]  # idle: what it really holds
+        avail = self.budget - (self._reserved - held)
         take = min(len(q), self.max_batch)
-        while take > 0 and self.footprint(n, op, take) > free:
+        trim = False
+        while take > 0:
+            need = self.footprint(n, op, take)
+            if held + need <= avail:
+                break
+            if need <= avail and held > 0:
+                trim = True  # fits once the lane has released what it holds
+                break
             take //= 2
         if take == 0:
-            if self._in_flight == 0 and self.footprint(n, op, 1) > self.budget:
-                # can never fit: fail this request alone
-                heapq.heappop(self._heads)
-                r = q.popleft()
-                if q:
-                    self._push_head(q[0].arrival, best)
-                r.future.set_exception(LweError("request needs more device memory than the budget (LWE_ENOMEM)"))
-                return self._pick_group()
+            if self._in_flight == 0:
+                idle_held = sum(self._commit[x] for x in self._free_lanes)
+                if self.footprint(n, op, 1) > self.budget - (self._reserved - idle_held):
+                    # even with every lane trimmed this request cannot fit: fail it alone
+                    heapq.heappop(self._heads)
+                    r = q.popleft()
+                    if q:
+                        self._push_head(q[0].arrival, best)
+                    r.future.set_exception(
+                        LweError("request needs more device memory than the budget (LWE_ENOMEM)"))
+                    return self._pick_group(lane)
+                if idle_held:
+                    # memory held by idle lanes blocks it: release it all and try again
+                    for x in self._free_lanes:
+                        self._trim_lane(x)
+                    return self._pick_group(lane)
             return None
         heapq.heappop(self._heads)
         reqs = [q.popleft() for _ in range(take)]
         if q:
             self._push_head(q[0].arrival, best)
-        return best, reqs, self.footprint(n, op, take)
+        need = self.footprint(n, op, take)
+        return best, reqs, (need if trim else held + need), trim
+
+    def _trim_lane(self, lane: int) -> None:
+        """Releases an idle lane's memory (caller holds the lock)."""
+        self.backend.trim(lane)
+        held = int(self.backend.held_bytes(lane))
+        self._reserved += held - self._commit[lane]
+        self._commit[lane] = held
+        self.trims += 1
 
     def _loop(self) -> None:
         while True:
@@ -189,21 +260,26 @@ class Server:
                 while True:
                     if self._stop and not any(self._queues.values()) and self._in_flight == 0:
                         return
-                    if self._free_lanes:
-                        g = self._pick_group()
+                    if self._free_lanes and not self._paused:
+                        g = self._pick_group(self._free_lanes[-1])
                         if g is not None:
                             break
                     self._cv.wait(timeout=0.05)
-                (op, n, key), reqs, fp = g
+                (op, n, key), reqs, cap, trim = g
                 lane = self._free_lanes.pop()
-                self._reserved += fp
+                if trim:
+                    self._trim_lane(lane)
+                    cap = max(cap, self._commit[lane])
+                self.backend.limit_lane(lane, cap)
+                self._reserved += cap - self._commit[lane]
+                self._commit[lane] = cap
                 self._in_flight += 1
                 self.max_reserved = max(self.max_reserved, self._reserved)
                 self.max_in_flight_groups = max(self.max_in_flight_groups, self._in_flight)
                 self.groups.append((op, n, key, len(reqs)))
-            self._pool.submit(self._run_group, lane, op, n, key, reqs, fp)
+            self._pool.submit(self._run_group, lane, op, n, key, reqs)
 
-    def _run_group(self, lane: int, op: int, n: int, key: int, reqs: List[Request], fp: int) -> None:
+    def _run_group(self, lane: int, op: int, n: int, key: int, reqs: List[Request]) -> None:
         t0 = self.clock()
         for r in reqs:
             r.start = t0
@@ -214,8 +290,11 @@ class Server:
         except Exception as e:  # the whole group failed: report it to each of its requests
             results, err = None, e
         t1 = self.clock()
+        held = int(self.backend.held_bytes(lane))  # the lane is idle again: what it really holds
         with self._cv:
-            self._reserved -= fp
+            self._reserved += held - self._commit[lane]
+            self._commit[lane] = held
+            self.max_held = max(self.max_held, self._reserved)
             self._in_flight -= 1
             self._free_lanes.append(lane)
             for i, r in enumerate(reqs):
@@ -271,6 +350,18 @@ class LibraryBackend(Backend):
 
     def lanes(self) -> int:
         return len(self._lanes)
+
+    def held_bytes(self, lane: int) -> int:
+        return self._lanes[lane].device_bytes
+
+    def limit_lane(self, lane: int, cap: int) -> None:
+        self._lanes[lane].set_budget(0 if cap <= 0 else max(int(cap), 1024))
+
+    def trim(self, lane: int) -> None:
+        self._lanes[lane].trim()
+
+    def call_bytes(self, n: int, op: int, count: int) -> Optional[int]:
+        return self._lanes[0].call_bytes(self.pids[n], op, count)
 
     def host_key(self, n: int, key: int):
         return self.keys[n][key][2], self.keys[n][key][3]

@@ -138,7 +138,7 @@ def test_decrypt(ctx, orc, n):
     assert np.array_equal(out, mus)
 
 
-@pytest.mark.parametrize("n", [200, 640, 976, 1344])
+@pytest.mark.parametrize("n", [200, 640, 976, 1344, 4096])
 @pytest.mark.parametrize("count", [1, 4])
 def test_keygen(ctx, orc, n, count):
     lp, op = _pair(orc, n)
@@ -373,9 +373,11 @@ def test_argument_checks(ctx, orc):
 
 def test_full_batch_4096_sampled(ctx, orc):
     """The benchmark's batched configuration at full size: 4096 encapsulations at n = 1344 in
-    one call (strip product with the tuned tile shape), checked against the oracle at sampled
-    instances (both ends, both parities of a 16-row MFMA tile, row-chunk boundaries), then all
-    4096 decapsulated on the device (KEM invariant) and a sample of them by the oracle."""
+    one call (strip product with the tuned tile shape), checked against the oracle at 72
+    instances: every 64th instance alternating between the two instances of a 16-row MFMA tile
+    (so every row chunk of the strip kernel and both tile parities), both ends and the
+    row-chunk boundaries; then all 4096 decapsulated on the device (KEM invariant) and a
+    sample of them by the oracle."""
     lp, op = _pair(orc, 1344)
     g = lwe_inputs.rng(0, 4096)
     pk, sk = _keypair(orc, op, g)
@@ -385,7 +387,10 @@ def test_full_batch_4096_sampled(ctx, orc):
     ss = np.zeros((count, 32), np.uint8)
     say("full batch encaps 4096")
     ctx.encaps_batch(lp.pid, count, pk, mus, ct, ss)
-    for i in [0, 1, 511, 512, 2047, 2048, 3071, 4095]:
+    picks = sorted(set([64 * k + (k % 2) for k in range(64)] + [0, 1, 511, 512, 2047, 2048, 3071, 4095]))
+    assert len(picks) >= 64
+    say("oracle on", len(picks), "instances")
+    for i in picks:
         oct_, oss = orc.kem_encaps(op, pk, mus[i].tobytes())
         assert ct[i].tobytes() == oct_ and ss[i].tobytes() == oss, i
     ss2 = np.zeros((count, 32), np.uint8)

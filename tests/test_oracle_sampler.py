@@ -72,3 +72,30 @@ def test_stream_is_sampler_of_keystream(orc):
     words = orc.ctr_words(key, 2, 11, 300)
     got = orc.sample_stream(p, key, 2, 11, 300)
     assert np.array_equal(got, [orc.sample_word(int(u), T, p.K) for u in words])
+
+
+@pytest.mark.parametrize("n", REGISTRY)
+def test_table_is_nearest_15_bit_cdf(orc, n):
+    """Each entry is pinned exactly, not just near its target: the sampler gives |e| <= k with
+    probability (T[k] + 1) / 2^15 (the exhaustive histogram above), and that probability must
+    be the 15-bit value nearest to the truncated discrete Gaussian's P(|x| <= k).  Here the
+    Gaussian sums are evaluated in 50-digit decimal arithmetic, a separate route from the
+    oracle's IEEE double sums; a dropped -1, a floor in place of rounding, or a normalisation
+    over the wrong support moves some entry by at least one and fails."""
+    from decimal import Decimal, getcontext
+
+    getcontext().prec = 50
+    p = orc.params_for(n)
+    T = orc.cdf_table(p.K, p.sigma).astype(np.int64)
+    s2 = 2 * Decimal(repr(p.sigma)) ** 2
+    w = [(-Decimal(x * x) / s2).exp() for x in range(p.K + 1)]
+    total = w[0] + 2 * sum(w[1:])
+    acc = Decimal(0)
+    for k in range(p.K):
+        acc += w[k] if k == 0 else 2 * w[k]
+        target = Decimal(32768) * acc / total
+        # not a near-tie, so that double and decimal rounding cannot disagree
+        frac = target - int(target)
+        assert abs(frac - Decimal("0.5")) > Decimal("1e-9"), (k, target)
+        assert abs(Decimal(int(T[k]) + 1) - target) <= Decimal("0.5"), (k, int(T[k]), target)
+    assert T[p.K] == 32767

@@ -113,3 +113,63 @@ def test_latency_accounting_uses_arrival():
         f.result(timeout=5)
         lat = s.latency_ms()
     assert lat.size == 1 and lat[0] >= 4.9
+
+
+class FakeMemBackend(FakeBackend):
+    """Lanes that keep device memory between groups, as library contexts do: a group grows
+    the lane's holding to at least its footprint and nothing shrinks until trim().  run()
+    fails if the group would need more than the cap the server set for the lane, and the
+    total held by all lanes is checked against the budget at every change."""
+
+    def __init__(self, lanes, budget, base=1024, delay=0.005):
+        super().__init__(lanes=lanes, delay=delay)
+        self.budget = budget
+        self.base = base
+        self.held = [base] * lanes
+        self.cap = [0] * lanes
+        self.max_total = sum(self.held)
+        self.trim_calls = 0
+
+    def held_bytes(self, lane):
+        return self.held[lane]
+
+    def limit_lane(self, lane, cap):
+        self.cap[lane] = cap
+
+    def trim(self, lane):
+        with self.lock:
+            self.held[lane] = self.base
+            self.trim_calls += 1
+
+    def call_bytes(self, n, op, count):
+        return self.base + count * n
+
+    def run(self, lane, op, n, key, payloads):
+        need = self.call_bytes(n, op, len(payloads))
+        with self.lock:
+            grown = self.held[lane] + need - self.base if self.held[lane] < need else self.held[lane]
+            if self.cap[lane] and grown > self.cap[lane]:
+                raise LweError("over the lane cap")
+            self.held[lane] = grown
+            self.max_total = max(self.max_total, sum(self.held))
+            assert sum(self.held) <= self.budget
+        return super().run(lane, op, n, key, payloads)
+
+
+def test_admission_bounds_memory_held_between_groups():
+    """Lanes keep what they allocated (the largest group they ran); the server admits by
+    those real holdings, trims idle lanes when they block a group, and the memory held by
+    all lanes together never exceeds the budget."""
+    budget = 3 * 1024 + 4096 * 12
+    be = FakeMemBackend(lanes=3, budget=budget)
+    with Server(be, hbm_budget=budget, max_batch=64) as s:
+        futs = []
+        for i in range(400):
+            n = (640, 976, 4096)[i % 3]
+            futs.append(s.submit((ENCAPS, DECAPS)[i % 2], n, i % 2, (i,)))
+        for f in futs:
+            f.result(timeout=30)
+        assert s.max_reserved <= budget and s.max_held <= budget
+    assert be.max_total <= budget
+    assert be.trim_calls > 0  # holdings of idle lanes had to be released
+    assert max(g[3] for g in s.groups) > 1
