@@ -18,6 +18,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lwe_oracle.c")
+_SRC_PB = os.path.join(_HERE, "lwe_oracle_pb.c")
 _LIB_PATH = os.path.join(_HERE, "liblwe_oracle.so")
 NBAR = 8
 MBAR = 8
@@ -26,11 +27,11 @@ MBAR = 8
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (OpenMP threaded outer loops)."""
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < max(
-        os.path.getmtime(_SRC), os.path.getmtime(os.path.join(_HERE, "lwe_oracle.h"))
+        os.path.getmtime(_SRC), os.path.getmtime(_SRC_PB), os.path.getmtime(os.path.join(_HERE, "lwe_oracle.h"))
     ):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         subprocess.check_call(
-            ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-o", tmp, _SRC, "-lm"]
+            ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-o", tmp, _SRC, _SRC_PB, "-lm"]
         )
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -115,6 +116,11 @@ def lib():
             "orc_kem_decaps": (C.c_int, [P, u8p, u8p, u8p]),
             "orc_fo_coins": (None, [P, u8p, u8p, u8p, u8p]),
             "orc_threads": (C.c_int, []),
+            "orc_aes256_expand_key": (None, [u8p, u8p]),
+            "orc_aes256_encrypt": (None, [u8p, u8p, u8p]),
+            "orc_drbg_instantiate": (None, [u8p, u8p, u8p]),
+            "orc_drbg_generate": (None, [u8p, u8p, C.c_size_t, u8p]),
+            "orc_drbg_words": (None, [u8p, C.c_uint32, C.c_size_t, u8p]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)
@@ -296,3 +302,35 @@ def fo_coins(p: Params, pkh: bytes, mu: bytes):
     kp = (C.c_uint8 * 32)()
     lib().orc_fo_coins(C.byref(p._c()), _buf(pkh), _buf(mu), coins, kp)
     return bytes(coins), bytes(kp)
+
+
+# ---- AES-256 and the CTR_DRBG noise source ----------------------------------------------
+def aes256_encrypt(key: bytes, block: bytes) -> bytes:
+    rk = (C.c_uint8 * 240)()
+    lib().orc_aes256_expand_key(_buf(key), rk)
+    out = (C.c_uint8 * 16)()
+    lib().orc_aes256_encrypt(rk, _buf(block), out)
+    return bytes(out)
+
+
+def drbg_instantiate(entropy: bytes):
+    """(Key, V) after Instantiate with a 48-byte entropy input (no personalization)."""
+    key = (C.c_uint8 * 32)()
+    V = (C.c_uint8 * 16)()
+    lib().orc_drbg_instantiate(_buf(entropy), key, V)
+    return bytes(key), bytes(V)
+
+
+def drbg_generate(key: bytes, V: bytes, nbytes: int):
+    """One Generate request: (output, new Key, new V)."""
+    k = (C.c_uint8 * 32).from_buffer_copy(key)
+    v = (C.c_uint8 * 16).from_buffer_copy(V)
+    out = (C.c_uint8 * max(1, nbytes))()
+    lib().orc_drbg_generate(k, v, nbytes, out)
+    return bytes(out)[:nbytes], bytes(k), bytes(v)
+
+
+def drbg_words(key16: bytes, domain: int, nwords: int) -> np.ndarray:
+    out = np.zeros(max(1, nwords), np.uint16)
+    lib().orc_drbg_words(_buf(key16), domain, nwords, _ptr(out))
+    return out[:nwords]

@@ -657,3 +657,112 @@ int orc_kem_decaps(const orc_params* p, const uint8_t* sk, const uint8_t* ct, ui
   free(ct2);
   return keep ? 1 : 0;
 }
+
+/* ------------------------------------------------------------------------------------ */
+/* AES-256, FIPS-197 Sec. 5 with Nk = 8, Nr = 14: 60 key-schedule words (240 bytes).    */
+/* The paper's device noise source is an AES-256 DRBG (Sec. 3.3).                       */
+/* ------------------------------------------------------------------------------------ */
+void orc_aes256_expand_key(const uint8_t key[32], uint8_t rk[240]) {
+  memcpy(rk, key, 32);
+  uint8_t rcon = 0x01;
+  for (int i = 8; i < 60; ++i) {
+    uint8_t t[4];
+    memcpy(t, rk + 4 * (i - 1), 4);
+    if (i % 8 == 0) {
+      uint8_t r0 = t[0]; /* RotWord */
+      t[0] = t[1];
+      t[1] = t[2];
+      t[2] = t[3];
+      t[3] = r0;
+      for (int b = 0; b < 4; ++b) t[b] = SBOX[t[b]]; /* SubWord */
+      t[0] ^= rcon;
+      rcon = xtime(rcon);
+    } else if (i % 8 == 4) {
+      for (int b = 0; b < 4; ++b) t[b] = SBOX[t[b]]; /* SubWord only (Nk > 6) */
+    }
+    for (int b = 0; b < 4; ++b) rk[4 * i + b] = rk[4 * (i - 8) + b] ^ t[b];
+  }
+}
+
+void orc_aes256_encrypt(const uint8_t rk[240], const uint8_t in[16], uint8_t out[16]) {
+  uint8_t s[16];
+  memcpy(s, in, 16);
+  add_round_key(s, rk);
+  for (int round = 1; round < 14; ++round) {
+    sub_bytes(s);
+    shift_rows(s);
+    mix_columns(s);
+    add_round_key(s, rk + 16 * round);
+  }
+  sub_bytes(s);
+  shift_rows(s);
+  add_round_key(s, rk + 224);
+  memcpy(out, s, 16);
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* CTR_DRBG with AES-256 and no derivation function (SP 800-90A Rev. 1, Sec. 10.2.1):    */
+/* seedlen = 384 bits, the counter is the whole 128-bit V (big endian), at most 2^19     */
+/* bits per Generate request, each request followed by an Update with zero additional   */
+/* input.  The paper draws its noise from such a generator (Sec. 3.3).                  */
+/* ------------------------------------------------------------------------------------ */
+static void v_increment(uint8_t V[16]) {
+  for (int k = 15; k >= 0; --k)
+    if (++V[k] != 0) break;
+}
+
+/* CTR_DRBG_Update (Sec. 10.2.1.2) */
+static void drbg_update(const uint8_t provided[48], uint8_t key[32], uint8_t V[16]) {
+  uint8_t rk[240], temp[48];
+  orc_aes256_expand_key(key, rk);
+  for (int b = 0; b < 3; ++b) {
+    v_increment(V);
+    orc_aes256_encrypt(rk, V, temp + 16 * b);
+  }
+  for (int k = 0; k < 48; ++k) temp[k] ^= provided[k];
+  memcpy(key, temp, 32);
+  memcpy(V, temp + 32, 16);
+}
+
+void orc_drbg_instantiate(const uint8_t entropy[48], uint8_t key[32], uint8_t V[16]) {
+  /* no personalization string: seed_material = entropy_input; Key = 0, V = 0 (Sec. 10.2.1.3.1) */
+  memset(key, 0, 32);
+  memset(V, 0, 16);
+  drbg_update(entropy, key, V);
+}
+
+void orc_drbg_generate(uint8_t key[32], uint8_t V[16], size_t nbytes, uint8_t* out) {
+  /* Sec. 10.2.1.5.1 with no additional input; nbytes <= 2^16 (2^19 bits) */
+  uint8_t rk[240], blk[16], zero[48];
+  orc_aes256_expand_key(key, rk);
+  for (size_t off = 0; off < nbytes; off += 16) {
+    v_increment(V);
+    orc_aes256_encrypt(rk, V, blk);
+    size_t m = nbytes - off < 16 ? nbytes - off : 16;
+    memcpy(out + off, blk, m);
+  }
+  memset(zero, 0, sizeof(zero));
+  drbg_update(zero, key, V);
+}
+
+/* Noise stream of (key, domain): a DRBG instantiated from the 48-byte entropy input      */
+/* key (16) || domain (4, little endian) || 28 zero bytes, read in requests of 2^16 bytes;*/
+/* word w is bytes 2w, 2w + 1 of the output (little endian).  Writes words 0 .. nwords-1.*/
+void orc_drbg_words(const uint8_t key16[16], uint32_t domain, size_t nwords, uint16_t* out) {
+  uint8_t entropy[48], key[32], V[16];
+  memset(entropy, 0, sizeof(entropy));
+  memcpy(entropy, key16, 16);
+  for (int k = 0; k < 4; ++k) entropy[16 + k] = (uint8_t)(domain >> (8 * k));
+  orc_drbg_instantiate(entropy, key, V);
+  const size_t REQ = 65536;
+  uint8_t* buf = (uint8_t*)malloc(REQ);
+  size_t done = 0;
+  while (done < nwords) {
+    size_t want = (nwords - done) * 2 < REQ ? (nwords - done) * 2 : REQ;
+    /* every request is a full 2^16 bytes (the stream does not depend on how much is read) */
+    orc_drbg_generate(key, V, REQ, buf);
+    for (size_t k = 0; k < want / 2; ++k) out[done + k] = (uint16_t)(buf[2 * k] | (buf[2 * k + 1] << 8));
+    done += want / 2;
+  }
+  free(buf);
+}

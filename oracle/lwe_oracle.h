@@ -115,6 +115,66 @@ void orc_fo_coins(const orc_params* p, const uint8_t pkh[32], const uint8_t* mu,
 /* number of OpenMP threads the oracle uses (1 if built without OpenMP) */
 int orc_threads(void);
 
+/* ---- AES-256 (FIPS-197, Nk = 8, Nr = 14) ---- */
+void orc_aes256_expand_key(const uint8_t key[32], uint8_t rk[240]);
+void orc_aes256_encrypt(const uint8_t rk[240], const uint8_t in[16], uint8_t out[16]);
+
+/* ---- CTR_DRBG, AES-256, no derivation function (SP 800-90A Rev. 1, Sec. 10.2.1) ---- */
+void orc_drbg_instantiate(const uint8_t entropy[48], uint8_t key[32], uint8_t V[16]);
+/* one Generate request of nbytes (<= 65536) without additional input */
+void orc_drbg_generate(uint8_t key[32], uint8_t V[16], size_t nbytes, uint8_t* out);
+/* Noise words 0 .. nwords-1 of (key, domain): a DRBG instantiated from key (16 bytes) ||
+ * domain (4 bytes, little endian) || 28 zero bytes and read in requests of 65536 bytes;
+ * word w = bytes 2w, 2w+1 of the output, little endian. */
+void orc_drbg_words(const uint8_t key16[16], uint32_t domain, size_t nwords, uint16_t* out);
+
+/* ======================================================================================
+ * The paper's own parameterisation (lwe_oracle_pb.c): one encryption per message bit
+ * (256 of them: nbar = 1, mbar = 256, one bit per coefficient), prime q from Table 1,
+ * s from the centred binomial distribution (eta), e, r, e1 from the discrete Gaussian of
+ * sigma (CDF table), e2 from the centred uniform distribution on [-k, k], all noise from
+ * the AES-256 CTR_DRBG above; A from AES-128-CTR(seedA) reduced mod q.
+ * ====================================================================================== */
+#define ORC_PB_BITS 256
+enum { ORC_PB_BINOMIAL = 0, ORC_PB_GAUSSIAN = 1, ORC_PB_UNIFORM = 2 };
+
+typedef struct {
+  int n;        /* lattice dimension */
+  int q;        /* prime modulus */
+  double sigma; /* Gaussian width of e, r, e1 */
+  int K;        /* support [-K, K] of the Gaussian's CDF table */
+  int k;        /* e2 uniform on [-k, k] */
+  int eta;      /* s binomial with parameter eta */
+} orc_pb_params;
+
+int orc_pb_params_for(int n, orc_pb_params* out); /* Table 1 rows n = 512 .. 32768 */
+int orc_pb_support(double sigma);                  /* largest K with a strictly increasing table */
+size_t orc_pb_coef_bytes(const orc_pb_params* p);  /* 2 if q < 2^16, else 4 */
+size_t orc_pb_pk_bytes(const orc_pb_params* p);
+size_t orc_pb_sk_bytes(const orc_pb_params* p);
+size_t orc_pb_ct_bytes(const orc_pb_params* p);
+int orc_pb_binomial(uint16_t w, int eta);
+int orc_pb_uniform(uint16_t w, int k);
+/* count samples of distribution dist (ORC_PB_*) from the noise words of (key, domain) */
+void orc_pb_noise(const orc_pb_params* p, const uint8_t key[16], uint32_t domain, int dist, size_t count,
+                  int16_t* out);
+void orc_pb_expand_A_cols(const orc_pb_params* p, const uint8_t seedA[16], int col0, int ncols, uint32_t* out);
+void orc_pb_pke_keygen(const orc_pb_params* p, const uint8_t seedA[16], const uint8_t seedSK[16], int16_t* s,
+                       uint32_t* t);
+void orc_pb_pke_encrypt(const orc_pb_params* p, const uint8_t seedA[16], const uint32_t* t, const uint8_t coins[16],
+                        const uint8_t* mu, uint32_t* U /* 256 x n */, uint32_t* v /* 256 */);
+int orc_pb_decode(int q, uint32_t x);
+void orc_pb_pke_decrypt(const orc_pb_params* p, const int16_t* s, const uint32_t* U, const uint32_t* v,
+                        uint8_t* mu);
+long orc_pb_noise_max(const orc_pb_params* p, const uint8_t seedSK[16], const uint8_t coins[16]);
+uint32_t orc_pb_t_entry(const orc_pb_params* p, const uint8_t seedA[16], const uint8_t seedSK[16], long i);
+uint32_t orc_pb_u_entry(const orc_pb_params* p, const uint8_t seedA[16], const uint8_t coins[16], int r, long j);
+void orc_pb_kem_keygen(const orc_pb_params* p, const uint8_t seedA[16], const uint8_t seedSK[16],
+                       const uint8_t z[32], uint8_t* pk, uint8_t* sk);
+void orc_pb_kem_encaps(const orc_pb_params* p, const uint8_t* pk, const uint8_t mu[32], uint8_t* ct,
+                       uint8_t ss[32]);
+int orc_pb_kem_decaps(const orc_pb_params* p, const uint8_t* sk, const uint8_t* ct, uint8_t ss[32]);
+
 #ifdef __cplusplus
 }
 #endif
