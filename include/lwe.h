@@ -245,6 +245,23 @@ typedef struct {
 int lwe_set_tuning(lwe_ctx* ctx, int pid, const lwe_tuning* t);
 int lwe_get_tuning(lwe_ctx* ctx, int pid, lwe_tuning* t);
 
+/* Decapsulation that allocates nothing, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * It computes exactly what lwe_decaps_batch computes (the same kernels), on the current
+ * device, with the working memory (decrypted messages, coins, round keys, S', E', E'',
+ * compare flags, ciphertext hashes, split-K accumulator) taken from one static device array
+ * of LWE_NOALLOC_SCRATCH_BYTES per device, which the library holds until the process ends.
+ *   sk, ct, ss: device pointers only (LWE_EINVAL otherwise); layouts as lwe_decaps_batch.
+ *   hip_stream: the stream the work is queued on; NULL = the null stream, synchronous.
+ * Returns LWE_ENOMEM, before launching anything, when count instances need more than the
+ * array holds (at n = 1344 about 1,500 instances).  The first call on a device sets the
+ * array up there (symbol lookup and a 1 KB table copy).  Every call on a device shares its
+ * array, whose contents the next call overwrites: calls that overlap on one device (other
+ * streams, other threads) race and must be ordered by the caller. */
+#define LWE_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+int lwe_decaps_batch_noalloc(int pid, size_t count, const uint8_t* sk, const uint8_t* ct, uint8_t* ss,
+                             void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,7 +9,9 @@ from .lwe import (  # noqa: F401
     LweError,
     LweLibraryMissing,
     Params,
+    NOALLOC_SCRATCH_BYTES,
     cdf_table,
+    decaps_batch_noalloc,
     lib,
     param_id,
     params,

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -52,6 +53,11 @@ struct lwe_ctx {
   bool async_alloc = false;    // the device supports stream-ordered allocation
   size_t budget = 0;  // 0 = unlimited; bounds held
   size_t held = 0;    // device bytes held: the growable buffers plus the AES table (T0_BYTES)
+  // Fixed arena (no-allocation calls): when set, buffers are carved from [arena, arena +
+  // arena_cap) for the duration of one call and nothing is allocated or freed.
+  uint8_t* arena = nullptr;
+  size_t arena_cap = 0, arena_used = 0;
+  bool device_hash_only = false;  // never hash on the host (no host staging)
   uint32_t* d_T0 = nullptr;
   Buf bufs[B_COUNT];
   // cache of the last public key hashed on the host
@@ -110,6 +116,18 @@ bool is_device_ptr(const void* p) {
 int ensure(lwe_ctx* c, BufId id, size_t bytes, void** out) {
   Buf& b = c->bufs[id];
   if (bytes == 0) bytes = 16;
+  if (c->arena) {
+    // carve from the fixed arena; a buffer asked for again in the same call keeps its region
+    if (b.cap < bytes) {
+      const size_t off = (c->arena_used + 255) & ~(size_t)255;
+      if (off > c->arena_cap || bytes > c->arena_cap - off) return LWE_ENOMEM;
+      b.p = c->arena + off;
+      b.cap = bytes;
+      c->arena_used = off + bytes;
+    }
+    *out = b.p;
+    return LWE_OK;
+  }
   if (b.cap < bytes) {
     size_t want = std::max(bytes, b.cap + b.cap / 2);
     want = (want + 255) & ~(size_t)255;
@@ -239,7 +257,7 @@ struct CallScope {
     c->cur = s;
   }
   ~CallScope() {
-    if (hipEventRecord(c->ev_done, s) == hipSuccess) c->last = s;
+    if (c->ev_done && hipEventRecord(c->ev_done, s) == hipSuccess) c->last = s;
     c->cur = outer;
   }
 };
@@ -318,6 +336,7 @@ void host_for(int threads, size_t count, F f) {
 const lwe_tuning& tuning_of(lwe_ctx* c, int pid) { return c->tuning[pid & 255]; }
 
 bool use_host_hash(lwe_ctx* c, int pid, size_t count) {
+  if (c->device_hash_only) return false;
   const lwe_tuning& t = tuning_of(c, pid);
   const size_t lim = t.host_hash_max ? t.host_hash_max : 16;
   return count <= lim;
@@ -1371,3 +1390,68 @@ int lwe_encaps_rand(lwe_ctx* c, int pid, size_t count, const uint8_t* pk, uint8_
 }
 
 }  // extern "C"
+
+// =====================================================================================
+// No-allocation decapsulation: the working memory of lwe_decaps_batch taken from a fixed
+// device array instead of a context's growable buffers.
+// =====================================================================================
+static __device__ __align__(256) uint8_t scratch[LWE_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+uint8_t* g_noalloc_ptr[NOALLOC_MAX_DEVICES];
+
+// Device address of the current device's copy of `scratch`, set up once per device: the
+// address comes from hipGetSymbolAddress (the array's name is only a host-side stand-in), and
+// the first T0_BYTES receive the AES table.  The rest is the per-call arena.
+int noalloc_base(int dev, uint8_t** out) {
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr ||
+        hipMemcpy(ptr, aes_T0(), T0_BYTES, hipMemcpyHostToDevice) != hipSuccess || init_kernels() != hipSuccess) {
+      (void)hipGetLastError();
+      return LWE_EDEVICE;
+    }
+    g_noalloc_ptr[dev] = (uint8_t*)ptr;
+  }
+  *out = g_noalloc_ptr[dev];
+  return LWE_OK;
+}
+
+}  // namespace
+
+extern "C" int lwe_decaps_batch_noalloc(int pid, size_t count, const uint8_t* sk, const uint8_t* ct,
+                                        uint8_t* ss, void* stream) {
+  const Params* pp;
+  LWE_CHECK(check_pid(pid, &pp));
+  if (count == 0) return LWE_OK;
+  if (!sk || !ct || !ss || count > LWE_MAX_BATCH) return LWE_EINVAL;
+  if (!is_device_ptr(sk) || !is_device_ptr(ct) || !is_device_ptr(ss)) return LWE_EINVAL;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+    (void)hipGetLastError();
+    return LWE_EDEVICE;
+  }
+  uint8_t* base = nullptr;
+  LWE_CHECK(noalloc_base(dev, &base));
+  // A transient context over the arena: device hashing on the caller's stream only (no host
+  // staging, no second stream), default tuning, no profiling.
+  lwe_ctx c;
+  memset(c.tuning, 0, sizeof(c.tuning));
+  c.device = dev;
+  c.use_side = false;
+  c.device_hash_only = true;
+  c.d_T0 = (uint32_t*)base;
+  c.arena = base + T0_BYTES;
+  c.arena_cap = LWE_NOALLOC_SCRATCH_BYTES - T0_BYTES;
+  // The arena holds what lwe_decaps_batch needs beyond its (device) inputs and output; the
+  // same sizes as lwe_ctx_call_bytes less the staging of sk, ct and ss.
+  auto r = [](size_t b) { return ((b ? b : 16) + 255) & ~(size_t)255; };
+  const size_t need = lwe_ctx_call_bytes(&c, pid, 2, count) - T0_BYTES - r(pp->sk_bytes) -
+                      r(count * pp->ct_bytes) - r(count * 32);
+  if (need > c.arena_cap) return LWE_ENOMEM;
+  return lwe_decaps_batch(&c, pid, count, sk, ct, ss, stream);
+}

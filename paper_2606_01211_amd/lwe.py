@@ -34,7 +34,7 @@ EXPORTS = [
     "lwe_test_expand_A", "lwe_test_keystream", "lwe_test_sample", "lwe_test_sample_batch",
     "lwe_test_product", "lwe_test_encrypt",
     "lwe_test_decrypt", "lwe_test_sha3", "lwe_set_tuning", "lwe_get_tuning",
-    "lwe_prof_enable", "lwe_prof_reset", "lwe_prof_read",
+    "lwe_prof_enable", "lwe_prof_reset", "lwe_prof_read", "lwe_decaps_batch_noalloc",
 ]
 
 KERNELS = ["sample", "prod_strip", "prod_strip_cmp", "prod_stream", "finalize", "decrypt", "fo_coins", "expand_keys",
@@ -127,6 +127,7 @@ def lib() -> C.CDLL:
         "lwe_prof_enable": (i32, [vp, i32]),
         "lwe_prof_reset": (i32, [vp]),
         "lwe_prof_read": (i32, [vp, C.c_char_p, C.POINTER(C.c_uint64), C.POINTER(C.c_double)]),
+        "lwe_decaps_batch_noalloc": (i32, [i32, sz, vp, vp, vp, vp]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -239,6 +240,22 @@ def _stream_ptr(args, stream) -> Optional[int]:
         torch = _torch()
         return torch.cuda.current_stream().cuda_stream
     return None
+
+
+# bytes of the static device array behind decaps_batch_noalloc (LWE_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 32 << 20
+
+
+def decaps_batch_noalloc(pid, count, sk, ct, ss, stream=None):
+    """lwe_decaps_batch_noalloc: decapsulation on the current device that allocates no device
+    memory (its working memory is the library's static per-device array).  sk, ct and ss must
+    be device tensors; the work is queued on `stream` (default: torch's current stream)."""
+    p = params(pid)
+    a = [_Arg(sk, p.sk_bytes), _Arg(ct, p.ct_bytes * count), _Arg(ss, 32 * count, True)]
+    if not all(x.device for x in a):
+        raise ValueError("decaps_batch_noalloc takes device tensors only")
+    st = _stream_ptr(a, stream)
+    _check(lib().lwe_decaps_batch_noalloc(pid, count, *[x.ptr for x in a], st), "lwe_decaps_batch_noalloc")
 
 
 class Context:
