@@ -132,6 +132,12 @@ class Server:
         self._seq = 0
         self._cv = threading.Condition()
         self._free_lanes = list(range(backend.lanes()))
+        # Lanes may arrive holding buffers grown under an earlier server; when those exceed
+        # this server's budget they are released first, so the budget bounds the memory the
+        # lanes hold from the start.
+        if sum(int(backend.held_bytes(lane)) for lane in range(backend.lanes())) > self.budget:
+            for lane in range(backend.lanes()):
+                backend.trim(lane)
         self._commit = [int(backend.held_bytes(lane)) for lane in range(backend.lanes())]
         self._reserved = sum(self._commit)
         self.max_reserved = self._reserved
@@ -199,52 +205,52 @@ class Server:
     def _pick_group(self, lane: int) -> Optional[Tuple[Tuple[int, int, int], List[Request], int, bool]]:
         """Oldest queue head first; as many of its requests as fit the budget on idle lane
         `lane`.  Returns (queue key, requests, cap for the lane, trim the lane first)."""
-        while self._heads:
-            arrival, seq, best = self._heads[0]
-            q = self._queues.get(best)
-            if not q or q[0].arrival != arrival:  # stale entry
-                heapq.heappop(self._heads)
-                continue
-            break
-        else:
-            return None
-        op, n, key = best
-        held = self._commit[lane]  # idle: what it really holds
-        avail = self.budget - (self._reserved - held)
-        take = min(len(q), self.max_batch)
-        trim = False
-        while take > 0:
-            need = self.footprint(n, op, take)
-            if held + need <= avail:
-                break
-            if need <= avail and held > 0:
-                trim = True  # fits once the lane has released what it holds
-                break
-            take //= 2
-        if take == 0:
-            if self._in_flight == 0:
-                idle_held = sum(self._commit[x] for x in self._free_lanes)
-                if self.footprint(n, op, 1) > self.budget - (self._reserved - idle_held):
-                    # even with every lane trimmed this request cannot fit: fail it alone
+        while True:
+            while self._heads:
+                arrival, seq, best = self._heads[0]
+                q = self._queues.get(best)
+                if not q or q[0].arrival != arrival:  # stale entry
                     heapq.heappop(self._heads)
-                    r = q.popleft()
-                    if q:
-                        self._push_head(q[0].arrival, best)
-                    r.future.set_exception(
-                        LweError("request needs more device memory than the budget (LWE_ENOMEM)"))
-                    return self._pick_group(lane)
-                if idle_held:
-                    # memory held by idle lanes blocks it: release it all and try again
-                    for x in self._free_lanes:
-                        self._trim_lane(x)
-                    return self._pick_group(lane)
-            return None
-        heapq.heappop(self._heads)
-        reqs = [q.popleft() for _ in range(take)]
-        if q:
-            self._push_head(q[0].arrival, best)
-        need = self.footprint(n, op, take)
-        return best, reqs, (need if trim else held + need), trim
+                    continue
+                break
+            else:
+                return None
+            op, n, key = best
+            held = self._commit[lane]  # idle: what it really holds
+            avail = self.budget - (self._reserved - held)
+            take = min(len(q), self.max_batch)
+            trim = False
+            while take > 0:
+                need = self.footprint(n, op, take)
+                if held + need <= avail:
+                    break
+                if need <= avail and held > 0:
+                    trim = True  # fits once the lane has released what it holds
+                    break
+                take //= 2
+            if take > 0:
+                heapq.heappop(self._heads)
+                reqs = [q.popleft() for _ in range(take)]
+                if q:
+                    self._push_head(q[0].arrival, best)
+                need = self.footprint(n, op, take)
+                return best, reqs, (need if trim else held + need), trim
+            if self._in_flight:
+                return None  # wait for a group to complete and release its reservation
+            # every lane is idle: release what idle lanes hold and try again, unless that frees
+            # nothing (each lane keeps a floor, its AES table) -- then the head request can
+            # never fit, and it fails alone
+            idle_held = sum(self._commit[x] for x in self._free_lanes)
+            if self.footprint(n, op, 1) <= self.budget - (self._reserved - idle_held) and idle_held:
+                for x in self._free_lanes:
+                    self._trim_lane(x)
+                if sum(self._commit[x] for x in self._free_lanes) < idle_held:
+                    continue
+            heapq.heappop(self._heads)
+            r = q.popleft()
+            if q:
+                self._push_head(q[0].arrival, best)
+            r.future.set_exception(LweError("request needs more device memory than the budget (LWE_ENOMEM)"))
 
     def _trim_lane(self, lane: int) -> None:
         """Releases an idle lane's memory (caller holds the lock)."""

@@ -173,3 +173,34 @@ def test_admission_bounds_memory_held_between_groups():
     assert be.max_total <= budget
     assert be.trim_calls > 0  # holdings of idle lanes had to be released
     assert max(g[3] for g in s.groups) > 1
+
+
+def test_lanes_arriving_over_budget_are_released_first():
+    """Lanes that still hold buffers grown under an earlier, larger server are trimmed when a
+    server with a smaller budget starts, so its budget bounds the held memory from the start."""
+    budget = 3 * 1024 + 4096 * 6
+    be = FakeMemBackend(lanes=3, budget=10**9)
+    be.held = [1024 + 4096 * 40, 1024 + 4096 * 20, 1024]  # left over from a bigger server
+    be.budget = budget
+    with Server(be, hbm_budget=budget, max_batch=64) as s:
+        assert s.max_reserved <= budget
+        futs = [s.submit(ENCAPS, 640, i % 2, (i,)) for i in range(40)]
+        for f in futs:
+            f.result(timeout=30)
+        assert s.max_reserved <= budget and s.max_held <= budget
+    assert be.trim_calls >= 3
+
+
+def test_request_above_the_floor_fails_alone_without_spinning():
+    """Every lane keeps a floor that trimming cannot release (its AES table).  A request that
+    fits the budget only if that floor were released too fails alone with LWE_ENOMEM; the
+    scheduler neither spins nor stalls, and later requests that fit are still served."""
+    be = FakeMemBackend(lanes=3, budget=10**9)
+    tiny = be.call_bytes(640, ENCAPS, 1) + 2 * be.base - 1
+    be.budget = tiny
+    with Server(be, hbm_budget=tiny, max_batch=64) as s:
+        f = s.submit(ENCAPS, 640, 0, (0,))
+        with pytest.raises(LweError):
+            f.result(timeout=10)
+        g = s.submit(ENCAPS, 320, 0, (1,))
+        assert g.result(timeout=10)[0] == "r"
