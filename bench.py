@@ -8,17 +8,20 @@ versus plain (one instance per call), with p50/p99 latencies.
 One step = KeyGen of a fresh key pair + lwe_encaps_batch(4096) + lwe_decaps_batch(4096) on
 device-resident buffers: every stage of the hot path (A expansion, sampling, all products,
 decoding, re-encryption + comparison, FO hashing) runs inside the timed region.
-`value` = 4096 * steps / wall time of the timed steps, with --streams independent steps in
-flight (one library context and HIP stream per lane; each lane's context keeps all of its work
-on that one stream, so every lane has a hardware queue of its own).  `serial` is the same run
-on one lane, whose decapsulations overlap their ciphertext hash on the context's second stream
-and whose SHA3 kernels hash each record on two lanes (shorter latency); the pipelined lanes hash
-one record per thread (less work per record).
+`value` = 4096 * steps / wall time of the timed steps, with independent steps in flight on
+several lanes (one library context and HIP stream per lane; each lane's context keeps all of
+its work on that one stream, so every lane has a hardware queue of its own).  The lane count
+is the largest divisor of --steps not above --streams (at least half of it), so every lane
+runs the same number of timed steps; the feeding threads start together after the device
+has drained.  `serial` is the same K steps on one lane with the same kernels, and the
+per-kernel times, `roofline` and `fused_product` come from it (stand-alone times of the
+kernels behind `value`); `kernels_pipelined` has the same kernels' times in the pipelined run.
 
-Also reported: the plain path (lwe_encaps / lwe_decaps one instance per call), per-kernel
-device time from HIP events recorded by the library on its streams, the roofline of the
-dominant kernel, and the CPU oracle timed on this host over a bounded sample of the same
-workload (whose outputs are compared byte for byte with the GPU's).
+Also reported: the plain path (lwe_encaps / lwe_decaps one instance per call, wall and device
+time), the CPU oracle timed on this host over a bounded sample of the same workload (whose
+outputs are compared byte for byte with the GPU's), and under `extras` the other workloads:
+plain n = 640 KEMs with p50/p99, single large-n KEMs (fused, and unfused at the largest n) and
+the serving workload at 0.5 and 0.8 of its measured capacity.
 """
 from __future__ import annotations
 
@@ -57,20 +60,20 @@ def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=140,
-                    help="timed steps (spread round-robin over the streams; a multiple of --streams keeps "
-                         "the lanes even)")
+                    help="timed steps (spread round-robin over the lanes)")
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--n", type=int, default=1344)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--plain", type=int, default=300, help="plain encaps and decaps calls timed one by one")
-    ap.add_argument("--streams", type=int, default=14,
-                    help="independent steps in flight (one library context and HIP stream each); the "
-                         "serial rate (one stream) is always measured too")
+    ap.add_argument("--streams", type=int, default=20,
+                    help="most independent steps in flight (one library context and HIP stream each); "
+                         "the lane count is the largest divisor of --steps up to this; the serial rate "
+                         "(one lane) is always measured too")
     ap.add_argument("--lane-side-stream", action="store_true",
                     help="let the lanes' decapsulations hash on their context's second stream too "
                          "(two streams per lane)")
-    ap.add_argument("--lane-hash-lanes", type=int, default=1, choices=(1, 2),
-                    help="lanes per record of the pipelined lanes' SHA3 kernels (the serial run uses 2)")
+    ap.add_argument("--lane-hash-lanes", type=int, default=2, choices=(1, 2),
+                    help="lanes per record of the SHA3 kernels of every lane and of the serial run")
     ap.add_argument("--hw-queues", type=int, default=0,
                     help="HIP hardware queues of this process (GPU_MAX_HW_QUEUES, at most 32; default "
                          "streams + 3, or 2 * streams + 2 with --lane-side-stream): every stream in "
@@ -86,6 +89,18 @@ def parse():
                          "into device memory and the products read it back instead of regenerating it")
     ap.add_argument("--large-n", default="8192,16384,32768")
     ap.add_argument("--large-reps", type=int, default=3)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other workloads (plain n=640, large n fused/unfused, serving)")
+    ap.add_argument("--plain640", type=int, default=300, help="n=640 KEMs timed one by one")
+    ap.add_argument("--serve-seconds", type=float, default=6.0,
+                    help="duration of each serving run (0.5 and 0.8 of capacity); 0 skips serving")
+    ap.add_argument("--energy-seconds", type=float, default=3.0,
+                    help="duration of the pipelined run during which GPU power is sampled (0 skips it)")
+    ap.add_argument("--no-comparator", action="store_true", help="skip the all-cores CPU comparator")
+    ap.add_argument("--paper-n", default="512,1024,2048,4096,8192,16384,32768",
+                    help="the paper's own parameter sets (Table 1) timed under extras; empty skips them")
+    ap.add_argument("--paper", action="store_true",
+                    help="instead of the batched benchmark: the paper's own sets (--paper-n) only")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -104,18 +119,18 @@ def copy_calibration():
     return 0
 
 
-def large(args):
-    """Single KEMs at large n: per-phase wall and device time, and the AES keystream rate of
-    the regeneration of A (n^2/8 blocks per product pass)."""
+def large_runs(ctx, ns, reps, unfused, log=True):
+    """Single KEMs at large n on one context: per-phase wall and device time, and the AES
+    keystream rate of the regeneration of A (n^2/8 blocks per product pass).  With unfused,
+    the context's tuning expands A into device memory first (a_source = 1)."""
     import torch
 
     import lwe_inputs
     import paper_2606_01211_amd as L
 
     dev = torch.device("cuda:0")
-    ctx = L.Context(0)
-    out = {"mode": "large", "data": "synthetic", "runs": {}}
-    for n in [int(x) for x in args.large_n.split(",")]:
+    runs = {}
+    for n in ns:
         pid = L.param_id(n)
         p = L.params(pid)
         g = lwe_inputs.rng(2, n)
@@ -124,13 +139,14 @@ def large(args):
         ct = torch.empty(p.ct_bytes, dtype=torch.uint8, device=dev)
         ss = torch.empty(32, dtype=torch.uint8, device=dev)
         ss2 = torch.empty(32, dtype=torch.uint8, device=dev)
-        if args.unfused:
-            ctx.set_tuning(pid, a_source=1)
+        saved = ctx.get_tuning(pid)
+        if unfused:
+            ctx.set_tuning(pid, **dict(saved, a_source=1))
         phases = {"keygen": [], "encaps": [], "decaps": []}
         dev_ms = {"keygen": [], "encaps": [], "decaps": []}
         kern_ms = {"keygen": {}, "encaps": {}, "decaps": {}}
         ok = True
-        for rep in range(args.large_reps + 1):
+        for rep in range(reps + 1):
             sa, ssk, z = lwe_inputs.keygen_seeds(g, 1)
             mu = torch.from_numpy(lwe_inputs.messages(g, 1, p.mu_bytes)[0]).to(dev)
             calls = (("keygen", lambda: ctx.keygen(pid, sa[0], ssk[0], z[0], pk, sk)),
@@ -152,9 +168,11 @@ def large(args):
                     for k, (_, ms) in prof.items():
                         kern_ms[name].setdefault(k, []).append(ms)
             ok &= bool(torch.equal(ss, ss2))
-            print("n=%d rep %d done" % (n, rep), file=sys.stderr, flush=True)
+            if log:
+                print("n=%d rep %d done%s" % (n, rep, " (unfused)" if unfused else ""), file=sys.stderr, flush=True)
+        ctx.set_tuning(pid, **saved)
         blocks = n * n // 8
-        r = {"ok": ok, "aes_blocks_per_product": blocks, "a_source": "unfused" if args.unfused else "fused"}
+        r = {"ok": ok, "aes_blocks_per_product": blocks, "a_source": "unfused" if unfused else "fused"}
         for name in phases:
             wall = float(np.median(phases[name]))
             devt = float(np.median(dev_ms[name]))
@@ -162,38 +180,162 @@ def large(args):
                        "kernels_ms": {k: float(np.median(v)) for k, v in kern_ms[name].items()}}
         # one product pass (A regenerated once) in keygen and encaps, two in decaps (decrypt
         # reads no A; the re-encryption regenerates it once)
+        km = r["encaps"]["kernels_ms"]
+        prod_ms = km.get("prod_stream")
         r["keystream_GBps_encaps"] = blocks * 16 / (r["encaps"]["device_ms"] * 1e-3) / 1e9
-        if args.unfused:
+        if prod_ms and not unfused:
+            # the fused product kernel alone: its AES keystream rate and int8 MFMA rate (8 rows
+            # padded to 16 for the MFMA tile: 2 limbs x 2 ops x 16 x n x (n + 8) issued)
+            r["product_ms"] = prod_ms
+            r["product_keystream_GBps"] = blocks * 16 / (prod_ms * 1e-3) / 1e9
+            r["product_aes_Gblocks_s"] = blocks / (prod_ms * 1e-3) / 1e9
+        if unfused:
             # A (n^2 uint16) written once by the expansion and read once by the product
-            km = r["encaps"]["kernels_ms"]
             a_bytes = 2 * n * n
             r["unfused"] = {
                 "A_bytes": a_bytes,
                 "expand_A_ms": km.get("expand_A"),
                 "expand_A_write_GBps": a_bytes / (km["expand_A"] * 1e-3) / 1e9 if km.get("expand_A") else None,
-                "product_ms": km.get("prod_stream"),
-                "product_read_GBps": a_bytes / (km["prod_stream"] * 1e-3) / 1e9 if km.get("prod_stream") else None,
+                "product_ms": prod_ms,
+                "product_read_GBps": a_bytes / (prod_ms * 1e-3) / 1e9 if prod_ms else None,
+                "hbm_peak_GBps": PEAK_HBM_GBS,
             }
-        out["runs"][str(n)] = r
+        runs[str(n)] = r
+    return runs
+
+
+def large(args):
+    """CLI mode --large: single KEMs at large n."""
+    import paper_2606_01211_amd as L
+
+    ctx = L.Context(0)
+    out = {"mode": "large", "data": "synthetic",
+           "runs": large_runs(ctx, [int(x) for x in args.large_n.split(",")], args.large_reps, args.unfused)}
     ctx.close()
     print(json.dumps(out), flush=True)
     return 0
+
+
+class PowerSampler:
+    """Samples the GPU's board power while running: the hwmon power file of the first AMD GPU
+    (microwatts) every 50 ms when the kernel exposes one, else `amd-smi metric -p --json`
+    about once a second.  energy_j() integrates the samples over the sampled interval."""
+
+    def __init__(self):
+        import glob
+        import shutil
+
+        self.path = None
+        for cand in sorted(glob.glob("/sys/class/drm/card*/device/hwmon/hwmon*/power1_average")) + \
+                sorted(glob.glob("/sys/class/drm/card*/device/hwmon/hwmon*/power1_input")):
+            try:
+                if float(open(cand).read().strip()) > 0:
+                    self.path = cand
+                    break
+            except (OSError, ValueError):
+                continue
+        self.smi = shutil.which("amd-smi") or ("/opt/rocm/bin/amd-smi" if os.path.exists("/opt/rocm/bin/amd-smi") else None)
+        self.samples = []
+        self._stop = threading.Event()
+        self._th = None
+
+    def source(self):
+        return "hwmon:" + self.path if self.path else ("amd-smi" if self.smi else None)
+
+    def read_w(self):
+        if self.path:
+            try:
+                return float(open(self.path).read().strip()) * 1e-6
+            except (OSError, ValueError):
+                return None
+        if self.smi:
+            import re
+            import subprocess
+
+            try:
+                r = subprocess.run([self.smi, "metric", "-p", "--json"], capture_output=True, text=True, timeout=5)
+            except (OSError, subprocess.TimeoutExpired):
+                return None
+            # the socket power of GPU 0, whatever the nesting of this amd-smi version's JSON
+            m = re.search(r'"(?:socket_power|average_socket_power|current_socket_power)"\s*:\s*\{?[^0-9]*([0-9.]+)',
+                          r.stdout)
+            return float(m.group(1)) if m else None
+        return None
+
+    def _run(self):
+        period = 0.05 if self.path else 1.0
+        while not self._stop.is_set():
+            w = self.read_w()
+            if w is not None:
+                self.samples.append((time.perf_counter(), w))
+            self._stop.wait(period)
+
+    def start(self):
+        self._th = threading.Thread(target=self._run, daemon=True)
+        self._th.start()
+
+    def stop(self):
+        self._stop.set()
+        if self._th:
+            self._th.join()
+
+    def mean_w(self):
+        return float(np.mean([w for _, w in self.samples])) if self.samples else None
+
+
+def pick_lanes(steps, want):
+    """Lane count for `steps` timed steps: the largest count <= want that divides steps (and is
+    at least half of want), so that every lane runs the same number of timed steps; otherwise
+    want lanes with uneven shares (reported as lanes_even = false)."""
+    for s in range(min(want, steps), 0, -1):
+        if steps % s == 0 and s >= max(1, want // 2):
+            return s, True
+    return max(1, min(want, steps)), steps % max(1, min(want, steps)) == 0
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def main():
     args = parse()
     if args.copy_calibration:
         return copy_calibration()
-    # before anything initialises the GPU runtime
-    S = max(1, args.streams)
-    hwq = args.hw_queues if args.hw_queues > 0 else (2 * S + 2 if args.lane_side_stream else S + 3)
-    os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, max(1, hwq)))
     if args.gpus != 1:
         print("bench.py measures one GPU: the KEM hot path here runs on a single MI355X; "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         return 2
+    K, W = args.steps, args.warmup
+    S, lanes_even = pick_lanes(K, max(1, args.streams))
+    # before anything initialises the GPU runtime
+    hwq = args.hw_queues if args.hw_queues > 0 else (2 * S + 2 if args.lane_side_stream else S + 3)
+    os.environ["GPU_MAX_HW_QUEUES"] = str(min(32, max(1, hwq)))
     if args.large:
         return large(args)
+    if args.paper:
+        import torch
+
+        import paper_2606_01211_amd as L
+
+        ctx0 = L.Context(0)
+        out = {"mode": "paper", "data": "synthetic",
+               "runs": paper_runs(ctx0, L, torch, torch.device("cuda:0"), [int(x) for x in args.paper_n.split(",")])}
+        ctx0.close()
+        print(json.dumps(out), flush=True)
+        return 0
+    # The serving workload runs first, in a child process, while this process holds no GPU
+    # queues: the lanes' hardware queues of both processes together would exceed what the
+    # hardware scheduler maps at once, and time-sliced queues would distort the latencies.
+    serving = None
+    if not args.no_extras and args.serve_seconds > 0:
+        serving = serving_run(args)
+        print("extras: serving done", file=sys.stderr, flush=True)
     import torch
 
     import lwe_inputs
@@ -204,13 +346,11 @@ def main():
     pid = L.param_id(args.n)
     p = L.params(pid)
     B = args.batch
-    K, W = args.steps, args.warmup
     ctxs = [L.Context(0) for _ in range(S)]
-    # each lane runs on its context's own stream.  Lane 0 also times the serial rate, with the
-    # decapsulation hash overlapped on its context's second stream; in the pipelined run every
-    # lane keeps all of its work on its one stream (unless --lane-side-stream), so the lanes
-    # need one hardware queue each and more of them fit before queues are shared
-    for c in ctxs[1:]:
+    # Every lane (and the serial run on lane 0) uses the same kernels: all of a context's work
+    # on its one stream (unless --lane-side-stream) and --lane-hash-lanes lanes per record in
+    # the SHA3 kernels, so the serial run's kernel times describe the kernels behind `value`.
+    for c in ctxs:
         c.set_side_stream(args.lane_side_stream)
         c.set_hash_lanes(args.lane_hash_lanes)
     streams = [torch.cuda.ExternalStream(c.stream_handle, device=dev) for c in ctxs]
@@ -252,16 +392,20 @@ def main():
     def timed(lanes, first_seed):
         """K steps spread round-robin over `lanes` streams, each stream fed by its own host
         thread (a library call that hashes on the host waits for its own stream only; the
-        calls release the interpreter lock).  Returns wall seconds, per-step device
-        latencies (ms) and the merged kernel profile."""
+        calls release the interpreter lock).  The feeding threads are started first and
+        released together by a barrier, after the device has drained, so the timed window
+        holds the K steps and nothing else.  Returns wall seconds, per-step device latencies
+        (ms) and the merged kernel profile."""
         for c in ctxs:
             c.prof_reset()
             c.prof_enable(True)
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
         errors = []
+        go = threading.Barrier(lanes + 1)
 
         def feed(lane):
             try:
+                go.wait()
                 for i in range(lane, K, lanes):
                     with torch.cuda.stream(streams[lane]):
                         ev[i][0].record()
@@ -271,19 +415,17 @@ def main():
             except Exception as e:  # surfaced after the join
                 errors.append(e)
 
+        th = [threading.Thread(target=feed, args=(lane,)) for lane in range(lanes)]
+        for t in th:
+            t.start()
         torch.cuda.synchronize()
         # no collector pauses inside the timed region (they stall every feeding thread)
         gc.collect()
         gc.disable()
         t0 = time.perf_counter()
-        if lanes == 1:
-            feed(0)
-        else:
-            th = [threading.Thread(target=feed, args=(lane,)) for lane in range(lanes)]
-            for t in th:
-                t.start()
-            for t in th:
-                t.join()
+        go.wait()
+        for t in th:
+            t.join()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         gc.enable()
@@ -299,11 +441,10 @@ def main():
         return t1 - t0, [e0.elapsed_time(e1) for e0, e1 in ev], prof
 
     # ---------------- batched, timed ----------------
+    # serial: the same K steps on one lane (stand-alone kernel times of the same kernels)
     wall1, step_ms1, prof1 = timed(1, W)
     serial_value = K * B / wall1
     if S > 1:
-        ctxs[0].set_side_stream(args.lane_side_stream)
-        ctxs[0].set_hash_lanes(args.lane_hash_lanes)
         wall, step_ms, prof = timed(S, W + K)
     else:
         wall, step_ms, prof = wall1, step_ms1, prof1
@@ -311,8 +452,8 @@ def main():
     device_agree = all(bool(torch.equal(bf["ss"], bf["ss2"])) for bf in bufs)
     d_pk, d_sk, d_ct, d_ss = bufs[0]["pk"], bufs[0]["sk"], bufs[0]["ct"], bufs[0]["ss"]
     last_seed = W + K + (K - 1) - ((K - 1) % S) if S > 1 else W + K - 1  # last step run on lane 0
-    print("batched: %.1f encaps+decaps/s (%d streams), serial %.1f, %.3f ms/step" %
-          (value, S, serial_value, 1e3 * wall / K), file=sys.stderr, flush=True)
+    print("batched: %.1f encaps+decaps/s (%d lanes x %s steps), serial %.1f, %.3f ms/step" %
+          (value, S, K // S if lanes_even else "uneven", serial_value, 1e3 * wall / K), file=sys.stderr, flush=True)
 
     # ---------------- plain: one instance per call ----------------
     P = args.plain
@@ -335,20 +476,35 @@ def main():
         if i < 8:
             plain_ok &= bool(torch.equal(c1, d_ct[i])) and bool(torch.equal(s1, d_ss[i])) and bool(torch.equal(s1, s2))
     plain_rate = len(enc_ms) / (1e-3 * (sum(enc_ms) + sum(dec_ms)))
+    # device time of the same calls (kernel events on the context's streams), in a separate
+    # pass so that the events do not slow the timed one
+    dev_enc, dev_dec = [], []
+    for i in range(min(50, B)):
+        for name, fn, acc in (("encaps", lambda: ctx.encaps(pid, d_pk, d_mu[i], c1, s1), dev_enc),
+                              ("decaps", lambda: ctx.decaps(pid, d_sk, c1, s2), dev_dec)):
+            ctx.prof_reset()
+            ctx.prof_enable(True)
+            fn()
+            torch.cuda.synchronize()
+            acc.append(sum(ms for _, ms in ctx.prof_read().values()))
+            ctx.prof_enable(False)
     print("plain: %.1f encaps+decaps/s" % plain_rate, file=sys.stderr, flush=True)
 
     # ---------------- rooflines ----------------
     # Algorithmic work per timed step (one KeyGen, encaps_batch(B), decaps_batch(B)) of each
     # large kernel; achieved = K steps of work / the kernel's total device time in the serial
-    # run (HIP events on the launching streams).
+    # run (HIP events on the launching stream; the kernels are those of the pipelined lanes).
     n = p.n
     M = 8 * B
-    kern = {k: {"launches": v[0], "total_ms": v[1], "avg_us": 1e3 * v[1] / v[0]} for k, v in prof1.items()}
+
+    def kern_table(pr):
+        return {k: {"launches": v[0], "total_ms": v[1], "avg_us": 1e3 * v[1] / v[0]} for k, v in pr.items()}
+
+    kern = kern_table(prof1)
     ct_perms = -(-(p.ct_bytes + 1) // 136)
     work_per_step = {
         # strip product: the encapsulation (encryption) and the decapsulation's re-encryption
-        # (compare mode, sharing the GPU with that call's concurrent hash); each launch
-        # 2 limbs x (mul + add) x M x K x (n + 8)
+        # (compare mode); each launch 2 limbs x (mul + add) x M x K x (n + 8)
         "prod_strip": ("mfma", 2 * 2 * M * n * (n + 8)),
         "prod_strip_cmp": ("mfma", 2 * 2 * M * n * (n + 8)),
         # sampler: KeyGen (2n AES blocks) + two batched encryptions (2n + 8 blocks per instance)
@@ -376,6 +532,7 @@ def main():
         r["avg_us"] = kern[name]["avg_us"]
         r["launches_per_step"] = kern[name]["launches"] / K
         r["traffic"] = None
+        r["leg"] = "serial (one lane, the kernels of the pipelined lanes)"
         return r
 
     rooflines = {k: roofline_of(k) for k in work_per_step if k in kern}
@@ -384,6 +541,7 @@ def main():
     if "sample" in rooflines:
         blocks = 2 * n + 2 * B * (2 * n + 8)
         rooflines["sample"]["keystream_GBps"] = blocks * 16 / (kern["sample"]["total_ms"] * 1e-3 / K) / 1e9
+        rooflines["sample"]["aes_Gblocks_s"] = blocks / (kern["sample"]["total_ms"] * 1e-3 / K) / 1e9
     if "prod_strip" in rooflines:
         mch = ctx.get_tuning(pid)["m_chunks"] or 8
         fused = not args.unfused
@@ -398,11 +556,12 @@ def main():
         src = open(os.path.join(here, "paper_2606_01211_amd", "csrc", "kernels.hip"), "rb").read()
         if tr.get("kernels_source_sha256") == hashlib.sha256(src).hexdigest():
             tk = tr["kernels"]
+            hname = "k_hash_records_one" if args.lane_hash_lanes == 1 else "k_hash_records"
             by = {
                 "prod_strip": [tk.get("k_prod_strip<3, 2, false")],
                 "prod_strip_cmp": [tk.get("k_prod_strip<3, 2, true")],
                 "sample": [tk.get("k_sample<6>")],
-                "hash_records": [tk.get("k_hash_records")],
+                "hash_records": [tk.get(hname)],
                 "decrypt": [tk.get("k_decrypt")],
             }
             for k, ents in by.items():
@@ -414,10 +573,60 @@ def main():
         pass
     dominant = max(rooflines, key=lambda k: kern[k]["total_ms"])
     roof = rooflines[dominant]
+    # the fused AES + int8 MFMA contraction (encryption and compare launches)
+    fused_product = None
+    if "prod_strip" in rooflines:
+        fp = rooflines["prod_strip"]
+        fused_product = {"kernel": "k_prod_strip (A regenerated by AES-128-CTR in LDS, int8 MFMA)",
+                         "achieved_TOPS": fp["achieved"], "peak_TOPS": PEAK_INT8_TOPS, "frac": fp["frac"],
+                         "target_frac": 0.5, "avg_us": fp["avg_us"]}
+        if "prod_strip_cmp" in rooflines:
+            fused_product["compare_frac"] = rooflines["prod_strip_cmp"]["frac"]
+            fused_product["compare_avg_us"] = rooflines["prod_strip_cmp"]["avg_us"]
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "encaps+decaps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": 1e3 * wall / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic",
+        "config": {"workload": "batched-n%dx%d" % (n, B), "n": n, "logq": p.logq, "B": p.B, "batch": B,
+                   "nbar": 8, "mbar": 8, "step": "keygen + encaps_batch + decaps_batch",
+                   "A": "expanded once per call (unfused)" if args.unfused else "regenerated in the product (fused)"},
+        "bit_exact": None,
+        "batch_latency_ms": {"p50": pct(step_ms, 50), "p99": pct(step_ms, 99)},
+        "lanes": S,
+        "steps_per_lane": K // S if lanes_even else None,
+        "lanes_even": lanes_even,
+        "hw_queues": int(os.environ["GPU_MAX_HW_QUEUES"]),
+        "lane_side_stream": bool(args.lane_side_stream),
+        "lane_hash_lanes": int(args.lane_hash_lanes),
+        "serial": {"value": serial_value, "ms_per_step": 1e3 * wall1 / K,
+                   "batch_latency_ms": {"p50": pct(step_ms1, 50), "p99": pct(step_ms1, 99)}},
+        "plain": {"value": plain_rate, "unit": "encaps+decaps/s",
+                  "encaps_ms": {"p50": pct(enc_ms, 50), "p99": pct(enc_ms, 99)},
+                  "decaps_ms": {"p50": pct(dec_ms, 50), "p99": pct(dec_ms, 99)},
+                  "encaps_device_ms": {"p50": pct(dev_enc, 50), "p99": pct(dev_enc, 99)},
+                  "decaps_device_ms": {"p50": pct(dev_dec, 50), "p99": pct(dev_dec, 99)},
+                  "calls": len(enc_ms)},
+        "batched_over_plain": value / plain_rate,
+        "kernels": kern,
+        "kernels_pipelined": kern_table(prof),
+        "roofline": roof,
+        "fused_product": fused_product,
+        "rooflines": rooflines,
+        "cpu_baseline": None,
+    }
+    bit_exact = device_agree and plain_ok
 
     # ---------------- CPU oracle on a bounded sample ----------------
-    cpu = None
-    bit_exact = device_agree and plain_ok
     if not args.no_cpu:
         import oracle
 
@@ -438,47 +647,224 @@ def main():
             if time.perf_counter() - ta > args.cpu_seconds or done >= B:
                 break
         tcpu = time.perf_counter() - ta
-        cpu = {"value": done / tcpu, "unit": "encaps+decaps/s", "cores": oracle.threads(), "kind": "oracle",
-               "sample": "one keygen + %d encaps+decaps pairs of the last timed n=%d step (same seeds and mu), "
-                         "compared byte for byte with the GPU outputs" % (done, n)}
+        out["cpu_baseline"] = {
+            "value": done / tcpu, "unit": "encaps+decaps/s", "cores": oracle.threads(), "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": "one keygen + %d encaps+decaps pairs of the last timed n=%d step (same seeds and mu), "
+                      "compared byte for byte with the GPU outputs" % (done, n)}
+    out["bit_exact"] = bit_exact
 
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "encaps+decaps/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": W,
-        "ms_per_step": 1e3 * wall / K,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int8",
-        "data": "synthetic",
-        "config": {"workload": "batched-n%dx%d" % (n, B), "n": n, "logq": p.logq, "B": p.B, "batch": B,
-                   "nbar": 8, "mbar": 8, "step": "keygen + encaps_batch + decaps_batch",
-                   "A": "expanded once per call (unfused)" if args.unfused else "regenerated in the product (fused)"},
-        "bit_exact": bit_exact,
-        "batch_latency_ms": {"p50": pct(step_ms, 50), "p99": pct(step_ms, 99)},
-        "streams": S,
-        "hw_queues": int(os.environ["GPU_MAX_HW_QUEUES"]),
-        "lane_side_stream": bool(args.lane_side_stream),
-        "lane_hash_lanes": int(args.lane_hash_lanes),
-        "serial": {"value": serial_value, "ms_per_step": 1e3 * wall1 / K,
-                   "batch_latency_ms": {"p50": pct(step_ms1, 50), "p99": pct(step_ms1, 99)}},
-        "plain": {"value": plain_rate, "unit": "encaps+decaps/s",
-                  "encaps_ms": {"p50": pct(enc_ms, 50), "p99": pct(enc_ms, 99)},
-                  "decaps_ms": {"p50": pct(dec_ms, 50), "p99": pct(dec_ms, 99)}, "calls": len(enc_ms)},
-        "batched_over_plain": value / plain_rate,
-        "kernels": kern,
-        "roofline": roof,
-        "rooflines": rooflines,
-        "cpu_baseline": cpu,
-    }
+    # ---------------- all-cores CPU comparator on the same workload ----------------
+    if not args.no_comparator:
+        import cpu_comparator
+
+        kem = cpu_comparator.Kem(n, p.logq, p.B, p.K, p.sigma)
+        i_last = last_seed
+        ta = time.perf_counter()
+        cpk, csk = kem.keygen_batch(seedA[i_last:i_last + 1], seedSK[i_last:i_last + 1], z[i_last:i_last + 1])
+        cct, css = kem.encaps_batch(cpk[0], mus)
+        css2 = kem.decaps_batch(csk[0], cct)
+        tc = time.perf_counter() - ta
+        same = (cpk[0].tobytes() == d_pk.cpu().numpy().tobytes() and np.array_equal(cct, d_ct.cpu().numpy())
+                and np.array_equal(css, d_ss.cpu().numpy()) and np.array_equal(css, css2))
+        out["cpu_comparator"] = {
+            "value": B / tc, "unit": "encaps+decaps/s", "cores": cpu_comparator.threads(), "cpu_model": cpu_model(),
+            "kind": "all-cores OpenMP implementation (AES-NI, AVX2), not the oracle",
+            "sample": "one keygen + encaps_batch(%d) + decaps_batch(%d) of the last timed lane-0 step" % (B, B),
+            "bit_exact_vs_gpu": bool(same), "gpu_over_cpu": value / (B / tc)}
+        print("cpu comparator: %.1f encaps+decaps/s on %d threads" % (B / tc, cpu_comparator.threads()),
+              file=sys.stderr, flush=True)
+
+    # ---------------- energy: GPU power sampled over a longer pipelined run ----------------
+    if args.energy_seconds > 0:
+        ps = PowerSampler()
+        if ps.source() is None:
+            out["energy"] = {"error": "no GPU power source (hwmon power file or amd-smi) on this host"}
+        else:
+            idle = []
+            for _ in range(3 if ps.path else 1):
+                w = ps.read_w()
+                if w is not None:
+                    idle.append(w)
+                time.sleep(0.05)
+            done = [0] * S
+            stop_at = time.perf_counter() + args.energy_seconds
+
+            def spin(lane):
+                i = 0
+                while time.perf_counter() < stop_at:
+                    step(W + (i % (2 * K)), lane)
+                    i += 1
+                done[lane] = i
+
+            ps.start()
+            torch.cuda.synchronize()
+            e0 = time.perf_counter()
+            th = [threading.Thread(target=spin, args=(lane,)) for lane in range(S)]
+            for t in th:
+                t.start()
+            for t in th:
+                t.join()
+            torch.cuda.synchronize()
+            e1 = time.perf_counter()
+            ps.stop()
+            ops = sum(done) * B
+            pw = ps.mean_w()
+            out["energy"] = {
+                "source": ps.source(), "seconds": e1 - e0, "samples": len(ps.samples), "mean_power_w": pw,
+                "idle_power_w": float(np.mean(idle)) if idle else None, "ops": ops,
+                "ops_per_s": ops / (e1 - e0),
+                "energy_j": pw * (e1 - e0) if pw is not None else None,
+                "j_per_encaps_decaps": pw * (e1 - e0) / ops if pw is not None and ops else None,
+                "note": "board power of the GPU while the pipelined lanes run (not the host)"}
+        print("energy: %s" % json.dumps(out["energy"]), file=sys.stderr, flush=True)
+
+    # ---------------- the other workloads (plain n=640, large n, serving) ----------------
+    if not args.no_extras:
+        out["extras"] = extras(args, ctx, L, torch, dev)
+        if serving is not None:
+            out["extras"]["serving"] = serving
+
     for c in ctxs:
         c.close()
     print(json.dumps(out), flush=True)
     return 0
+
+
+def paper_runs(ctx, L, torch, dev, ns, reps=2):
+    """The paper's parameterisation: one encryption per message bit (256 rows per
+    ciphertext), prime q, DRBG noise.  Per n: wall and device time of KeyGen, Encaps and
+    Decaps (hashing on the host), per-kernel device time, and the product kernel's int8 MFMA
+    rate (2 limbs x 2 ops x 256 x n x n per encryption)."""
+    import lwe_inputs
+
+    runs = {}
+    for n in ns:
+        pid = L.param_id_paper(n)
+        p = L.params(pid)
+        g = lwe_inputs.rng(0, 8000 + n)
+        pk = torch.empty(p.pk_bytes, dtype=torch.uint8, device=dev)
+        sk = torch.empty(p.sk_bytes, dtype=torch.uint8, device=dev)
+        ct = torch.empty(p.ct_bytes, dtype=torch.uint8, device=dev)
+        ss = torch.empty(32, dtype=torch.uint8, device=dev)
+        ss2 = torch.empty(32, dtype=torch.uint8, device=dev)
+        wall = {"keygen": [], "encaps": [], "decaps": []}
+        devt = {"keygen": [], "encaps": [], "decaps": []}
+        kern = {"keygen": {}, "encaps": {}, "decaps": {}}
+        ok = True
+        for rep in range(reps + 1):
+            sa, ssk, z = lwe_inputs.keygen_seeds(g, 1)
+            mu = torch.from_numpy(lwe_inputs.messages(g, 1, 32)[0]).to(dev)
+            for name, fn in (("keygen", lambda: ctx.keygen(pid, sa[0], ssk[0], z[0], pk, sk)),
+                             ("encaps", lambda: ctx.encaps(pid, pk, mu, ct, ss)),
+                             ("decaps", lambda: ctx.decaps(pid, sk, ct, ss2))):
+                ctx.prof_reset()
+                ctx.prof_enable(True)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                prof = ctx.prof_read()
+                ctx.prof_enable(False)
+                if rep:
+                    wall[name].append(1e3 * (t1 - t0))
+                    devt[name].append(sum(ms for _, ms in prof.values()))
+                    for k, (_, ms) in prof.items():
+                        kern[name].setdefault(k, []).append(ms)
+            ok &= bool(torch.equal(ss, ss2))
+        r = {"q": p.q, "ct_bytes": p.ct_bytes, "decaps_agree": ok}
+        for name in wall:
+            r[name] = {"wall_ms": float(np.median(wall[name])), "device_ms": float(np.median(devt[name])),
+                       "kernels_ms": {k: float(np.median(v)) for k, v in kern[name].items()}}
+        prod = r["encaps"]["kernels_ms"].get("prod_stream", 0.0) + r["encaps"]["kernels_ms"].get("finalize", 0.0)
+        if prod:
+            r["encaps_product_TOPS"] = 2 * 2 * 256 * n * n / (prod * 1e-3) / 1e12
+            r["encaps_product_mfma_frac"] = r["encaps_product_TOPS"] / PEAK_INT8_TOPS
+        runs[str(n)] = r
+        print("paper n=%d done" % n, file=sys.stderr, flush=True)
+    return runs
+
+
+def extras(args, ctx, L, torch, dev):
+    """Plain n = 640 KEMs with p50/p99 (and the oracle on the same seeds), single large-n KEMs
+    fused and unfused, and the serving workload at 0.5 and 0.8 of its measured capacity (in a
+    child process with its own hardware-queue setting)."""
+    import lwe_inputs
+
+    ex = {}
+    # d1: n = 640, one keygen + encaps + decaps per seed set
+    n = 640
+    pid = L.param_id(n)
+    p = L.params(pid)
+    g = lwe_inputs.rng(0, 1)
+    R = args.plain640
+    sa, ssk, zz = lwe_inputs.keygen_seeds(g, R)
+    mus = lwe_inputs.messages(g, R, p.mu_bytes)
+    d_mus = torch.from_numpy(mus).to(dev)
+    pk = torch.empty(p.pk_bytes, dtype=torch.uint8, device=dev)
+    sk = torch.empty(p.sk_bytes, dtype=torch.uint8, device=dev)
+    ct = torch.empty(p.ct_bytes, dtype=torch.uint8, device=dev)
+    s1 = torch.empty(32, dtype=torch.uint8, device=dev)
+    s2 = torch.empty(32, dtype=torch.uint8, device=dev)
+    lat = {"keygen": [], "encaps": [], "decaps": []}
+    agree = True
+    for i in range(R + 1):
+        for name, fn in (("keygen", lambda: ctx.keygen(pid, sa[i % R], ssk[i % R], zz[i % R], pk, sk)),
+                         ("encaps", lambda: ctx.encaps(pid, pk, d_mus[i % R], ct, s1)),
+                         ("decaps", lambda: ctx.decaps(pid, sk, ct, s2))):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            if i:  # the first round grows the context's buffers
+                lat[name].append(1e3 * (time.perf_counter() - t0))
+        agree &= bool(torch.equal(s1, s2))
+    kem_ms = [a + b + c for a, b, c in zip(lat["keygen"], lat["encaps"], lat["decaps"])]
+    d1 = {"workload": "plain-n640", "kems": R, "kem_per_s": 1e3 * R / sum(kem_ms), "decaps_agree": agree}
+    for name, v in lat.items():
+        d1[name + "_ms"] = {"p50": pct(v, 50), "p99": pct(v, 99)}
+    d1["kem_ms"] = {"p50": pct(kem_ms, 50), "p99": pct(kem_ms, 99)}
+    if not args.no_cpu:
+        import oracle
+
+        op = oracle.params_for(n)
+        i = R % R  # the last round (i = R) ran the seeds and message of index 0
+        ta = time.perf_counter()
+        opk, osk = oracle.kem_keygen(op, sa[i].tobytes(), ssk[i].tobytes(), zz[i].tobytes())
+        oct_, oss = oracle.kem_encaps(op, opk, mus[i].tobytes())
+        oss2, ok = oracle.kem_decaps(op, osk, oct_)
+        tcpu = time.perf_counter() - ta
+        d1["bit_exact_last"] = (opk == pk.cpu().numpy().tobytes() and osk == sk.cpu().numpy().tobytes()
+                                and oct_ == ct.cpu().numpy().tobytes() and oss == s1.cpu().numpy().tobytes()
+                                and ok and oss2 == oss)
+        d1["oracle_kem_ms"] = 1e3 * tcpu
+    ex["plain_n640"] = d1
+    print("extras: n=640 plain done", file=sys.stderr, flush=True)
+    # d3: single large-n KEMs, fused, and the unfused comparison at the largest n
+    ns = [int(x) for x in args.large_n.split(",")]
+    ex["large_fused"] = large_runs(ctx, ns, 1, False)
+    ex["large_unfused"] = large_runs(ctx, ns[-1:], 1, True)
+    print("extras: large n done", file=sys.stderr, flush=True)
+    # the paper's own sets (Table 1): single KeyGen / Encaps / Decaps per n
+    if args.paper_n:
+        ex["paper_sets"] = paper_runs(ctx, L, torch, dev, [int(x) for x in args.paper_n.split(",")])
+        print("extras: paper sets done", file=sys.stderr, flush=True)
+    return ex
+
+
+def serving_run(args):
+    """The serving workload (capacity, then 0.5 and 0.8 of it) in a child process with its own
+    hardware-queue count."""
+    import subprocess
+
+    cmd = [sys.executable, "-m", "paper_2606_01211_amd.serve", "--duration", str(args.serve_seconds)]
+    try:
+        r = subprocess.run(cmd, cwd=ROOT, capture_output=True, text=True, timeout=300)
+        line = [x for x in r.stdout.splitlines() if x.startswith("{")]
+        return json.loads(line[-1]) if r.returncode == 0 and line else {"error": r.stderr[-2000:]}
+    except subprocess.TimeoutExpired:
+        return {"error": "timed out"}
 
 
 if __name__ == "__main__":

@@ -62,15 +62,26 @@ typedef enum {
   LWE_EUNSUPPORTED = -4  /* valid request that the library does not implement */
 } lwe_status;
 
-/* Parameter set description (Table 1 of the paper gives the prime-q sets it evaluated;
- * the sets registered here use q = 2^logq and a CDF-table error distribution). */
+/* Parameter set description.  Two families:
+ *  - matrix form (paper == 0; lwe_param_id): nbar = mbar = 8, q = 2^logq, B message bits
+ *    per coefficient, every secret and error from the 16-bit CDF table, noise from
+ *    AES-128-CTR;
+ *  - the paper's own sets (paper == 1; lwe_param_id_paper), Table 1: one encryption per
+ *    message bit (nbar = 1, mbar = 256, B = 1; Sec. 2.3, 3.2), prime q, s from the centred
+ *    binomial distribution (eta), e / r / e1 from the CDF table of sigma, e2 uniform on
+ *    [-k, k], all noise from an AES-256 CTR_DRBG (Sec. 3.3), decoding by Alg. 3's
+ *    thresholds q/4 and 3q/4.  Coefficients are serialised in coef_bytes bytes. */
 typedef struct {
   uint32_t n;      /* lattice dimension (multiple of 8) */
-  uint32_t logq;   /* q = 2^logq, 2 < logq <= 16 */
-  uint32_t B;      /* message bits per coefficient (64*B-bit messages) */
-  uint32_t K;      /* error support [-K, K] */
+  uint32_t logq;   /* matrix form: q = 2^logq, 2 < logq <= 16; paper sets: bits of q */
+  uint32_t B;      /* message bits per coefficient (mbar*nbar*B-bit messages) */
+  uint32_t K;      /* error support [-K, K] of the CDF table */
   double sigma;    /* width of the discrete Gaussian the 16-bit CDF table approximates */
   size_t pk_bytes, sk_bytes, ct_bytes, mu_bytes;
+  uint32_t paper;  /* 0 matrix form, 1 the paper's own set */
+  uint32_t q;      /* modulus */
+  uint32_t nbar, mbar, coef_bytes;
+  uint32_t eta, k; /* paper sets: binomial parameter of s, bound of e2 (0 otherwise) */
 } lwe_param_info;
 
 /* Create a context on HIP device `device`.  hbm_budget_bytes bounds the device memory the
@@ -118,8 +129,14 @@ int lwe_ctx_set_side_stream(lwe_ctx* ctx, int enable);
 int lwe_ctx_set_hash_lanes(lwe_ctx* ctx, int lanes);
 const char* lwe_strerror(int status);
 
-/* Parameter registry: id of the set for lattice dimension n, or a negative lwe_status. */
+/* Parameter registry: id of the matrix-form set for lattice dimension n, or a negative
+ * lwe_status. */
 int lwe_param_id(uint32_t n);
+/* Id of the paper's own set for n (Table 1: n = 512, 1024, 2048, 4096, 8192, 16384, 32768),
+ * or a negative lwe_status.  Every KEM entry point (and lwe_ctx_call_bytes) accepts these
+ * ids; the test hooks and lwe_decaps_batch_noalloc take matrix-form ids only
+ * (LWE_EUNSUPPORTED otherwise). */
+int lwe_param_id_paper(uint32_t n);
 /* Registers an additional parameter set (for experiments and tests; not security-vetted).
  * Requires n % 8 == 0, 8 <= n <= 32768, 3 <= logq <= 16, 1 <= B <= 8 with B < logq,
  * 1 <= K <= 15, sigma > 0, and a strictly increasing CDF table.  Returns the new id,
@@ -221,7 +238,8 @@ int lwe_test_sha3(lwe_ctx* ctx, size_t count, size_t len, const uint8_t* in, uin
  * "prod_strip_cmp" (the re-encryption and compare of a decapsulation),
  * "prod_stream", "finalize", "decrypt", "fo_coins", "expand_keys", "hash_records" (either
  * layout of lwe_ctx_set_hash_lanes), "final_ss", "fill", "keystream", "sample_stream",
- * "expand_A"), the number of launches and their summed device time since the last reset. */
+ * "expand_A"; for the paper's sets "drbg_chain", "pb_sample", "pb_rows", "pb_decrypt"), the
+ * number of launches and their summed device time since the last reset. */
 int lwe_prof_enable(lwe_ctx* ctx, int on);
 int lwe_prof_reset(lwe_ctx* ctx);
 int lwe_prof_read(lwe_ctx* ctx, const char* kernel, uint64_t* launches, double* total_ms);

@@ -156,14 +156,18 @@ void orc_pb_pke_encrypt(const orc_pb_params* p, const uint8_t seedA[16], const u
   const long long half = (p->q + 1) / 2;
 #pragma omp parallel for schedule(static)
   for (long r = 0; r < R; ++r) {
-    for (long j = 0; j < n; ++j) {
-      long long acc = E1[r * n + j];
-      for (long i = 0; i < n; ++i) acc += (long long)A[i * n + j] * Rm[r * n + i];
-      U[r * n + j] = mod_q(acc, p->q);
+    /* u_r[j] = e1_r[j] + sum_i A[i][j] r_r[i], accumulated row of A by row of A */
+    long long* acc = (long long*)malloc(sizeof(long long) * n);
+    for (long j = 0; j < n; ++j) acc[j] = E1[r * n + j];
+    for (long i = 0; i < n; ++i) {
+      const long long ri = Rm[r * n + i];
+      for (long j = 0; j < n; ++j) acc[j] += (long long)A[i * n + j] * ri;
     }
-    long long acc = (long long)e2[r] + (mu_bit(mu, (int)r) ? half : 0);
-    for (long i = 0; i < n; ++i) acc += (long long)t[i] * Rm[r * n + i];
-    v[r] = mod_q(acc, p->q);
+    for (long j = 0; j < n; ++j) U[r * n + j] = mod_q(acc[j], p->q);
+    free(acc);
+    long long vacc = (long long)e2[r] + (mu_bit(mu, (int)r) ? half : 0);
+    for (long i = 0; i < n; ++i) vacc += (long long)t[i] * Rm[r * n + i];
+    v[r] = mod_q(vacc, p->q);
   }
   free(A);
   free(Rm);

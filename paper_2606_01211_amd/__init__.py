@@ -14,6 +14,7 @@ from .lwe import (  # noqa: F401
     decaps_batch_noalloc,
     lib,
     param_id,
+    param_id_paper,
     params,
     register_params,
 )

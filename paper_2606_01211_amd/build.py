@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblwe_hip.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["kernels.hip", "api.cpp", "params.cpp"]
+SOURCES = ["kernels.hip", "kernels_paper.hip", "api.cpp", "params.cpp"]
 ARCH = os.environ.get("LWE_OFFLOAD_ARCH", "gfx950")
 
 

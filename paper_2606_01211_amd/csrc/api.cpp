@@ -24,7 +24,7 @@ constexpr size_t T0_BYTES = 1024;
 
 enum BufId {
   B_SEEDA, B_SEEDSK, B_Z, B_RKA, B_RK, B_X, B_E, B_E2, B_COINS, B_KP, B_HCT, B_FLAGS, B_MU2,
-  B_ACC, B_PK, B_SK, B_CT, B_MU, B_SS, B_PKH, B_TEST, B_AMAT, B_COUNT
+  B_ACC, B_PK, B_SK, B_CT, B_MU, B_SS, B_PKH, B_TEST, B_AMAT, B_CHAIN, B_ROWSUM, B_COUNT
 };
 
 struct Buf {
@@ -361,13 +361,14 @@ ProdPlan plan_product(lwe_ctx* c, int pid, const Params& p, ProdArgs& a, bool tr
   ProdPlan pl;
   const int ksteps = (p.n + 63) / 64;
   const lwe_tuning& tu = tuning_of(c, pid);
-  pl.strip = uses_strip(a.M, trans, a.per_inst_A != 0);
+  // the paper's sets (prime q) run on the streaming kernel only
+  pl.strip = !p.paper && uses_strip(a.M, trans, a.per_inst_A != 0);
   if (!pl.strip) {
     int RG = 1;
     if (!a.per_inst_A) RG = a.M <= 16 ? 1 : (a.M <= 32 ? 2 : 4);
     const int CG = 1;
-    a.m_tile = a.per_inst_A ? 8 : 16 * RG;
-    a.n_mt = a.per_inst_A ? a.M / 8 : (a.M + a.m_tile - 1) / a.m_tile;
+    a.m_tile = a.per_inst_A ? p.nbar : 16 * RG;
+    a.n_mt = a.per_inst_A ? a.M / p.nbar : (a.M + a.m_tile - 1) / a.m_tile;
     a.n_jt = (a.ncols + 16 * CG - 1) / (16 * CG);
     const long long units = (long long)a.n_jt * a.n_mt * ksteps;
     int KS = (int)std::max<long long>(1, (units + 65535) / 65536);
@@ -441,7 +442,7 @@ int run_product(lwe_ctx* c, int pid, const Params& p, ProdArgs a, bool trans, hi
   const lwe_tuning& tu = tuning_of(c, pid);
   // Unfused variant: expand A once into device memory and let the product read it (one A per
   // call, so not for key-generation batches, where every instance has its own A).
-  if (tu.a_source == 1 && (!a.per_inst_A || a.M == 8)) {
+  if (tu.a_source == 1 && !p.paper && (!a.per_inst_A || a.M == 8)) {
     uint16_t* Am;
     LWE_CHECK(ensure_t(c, B_AMAT, (size_t)p.n * p.n * 2, &Am));
     KLAUNCH("expand_A", s, launch_expand_A(p, a.rkA, a.T0, 0, (uint32_t)p.n, Am, s));
@@ -526,6 +527,339 @@ void host_pkh(lwe_ctx* c, const uint8_t* pk, size_t len, uint8_t out[32]) {
   sha3_256(pk, len, out);
   c->pk_cache.assign(pk, pk + len);
   memcpy(c->pkh_cache, out, 32);
+}
+
+// ------------------------------------------------------------------------------------
+// The paper's own sets (Table 1): one encryption per message bit, prime q, noise from the
+// AES-256 CTR_DRBG.  Hashing (H(pk), coins, K', H(ct), K) stays on the host: a ciphertext is
+// 256 (n + 1) coefficients (0.26 to 32 MB), a single sponge chain too long for one device lane.
+// ------------------------------------------------------------------------------------
+constexpr size_t DRBG_REQ_BYTES = (size_t)DRBG_REQ_BLOCKS * 16;
+
+// Generate requests of one noise stream of `words` 16-bit words
+int drbg_requests(size_t words) { return (int)((2 * words + DRBG_REQ_BYTES - 1) / DRBG_REQ_BYTES); }
+
+// Runs the DRBG chains of `count` instances (keys [count][16] on the device) for `nseg`
+// streams of the given word counts, then samples them into the destinations of `sa`
+// (dist, rowlen, dst8, inst_stride8, ld8, dst16 filled in by the caller).
+int pb_noise(lwe_ctx* c, const Params& p, size_t count, const uint8_t* dkeys, int nseg, const size_t words[3],
+             PbSampleArgs& sa, hipStream_t s) {
+  PbChainArgs ca;
+  memset(&ca, 0, sizeof(ca));
+  ca.nseg = nseg;
+  int rmax = 1;
+  for (int k = 0; k < nseg; ++k) {
+    ca.domain[k] = (uint32_t)(k + 1);
+    ca.requests[k] = drbg_requests(words[k]);
+    rmax = std::max(rmax, ca.requests[k]);
+  }
+  ca.rmax = rmax;
+  uint32_t* chain;
+  LWE_CHECK(ensure_t(c, B_CHAIN, count * nseg * (size_t)rmax * 64 * 4, &chain));
+  KLAUNCH("drbg_chain", s, launch_drbg_chain(dkeys, 16, (int)count, ca, c->d_T0, chain, s));
+  sa.count = (int)count;
+  sa.nseg = nseg;
+  sa.rmax = rmax;
+  for (int k = 0; k < nseg; ++k) sa.blocks[k] = (uint32_t)(words[k] / 8);
+  sa.eta = p.eta;
+  sa.ku = p.ku;
+  sa.K = p.K;
+  for (int k = 0; k <= MAX_K; ++k) sa.T[k] = p.T[k];
+  KLAUNCH("pb_sample", s, launch_pb_sample(sa, c->d_T0, chain, s));
+  return LWE_OK;
+}
+
+ProdArgs pb_prod_args(lwe_ctx* c, const Params& p) {
+  ProdArgs a;
+  memset(&a, 0, sizeof(a));
+  a.T0 = c->d_T0;
+  a.ldx = p.ldx;
+  a.n = p.n;
+  a.logq = p.logq;
+  a.B = p.B;
+  a.qp = p.q;
+  a.qp_magic = p.q < 65536 ? (uint32_t)((1ull << 32) / p.q + 1) : 0u;
+  a.coef_bytes = p.coef_bytes;
+  return a;
+}
+
+// Encryption of count messages under one public key (device pk record) with per-instance
+// coins [count][16] on the device: u_r = A^T r_r + e1_r and v_r = t^T r_r + e2_r + m_r
+// round(q/2) for r < 256 (Alg. 2 once per bit).  Writes ct records, or in compare mode sets
+// flags for records that differ from ct_cmp.
+int pb_encrypt_core(lwe_ctx* c, int pid, const Params& p, size_t count, const uint8_t* pk_dev, const uint8_t* dcoins,
+                    const uint8_t* mu_dev, size_t mu_stride, uint8_t* ct_out, const uint8_t* ct_cmp, uint32_t* flags,
+                    hipStream_t s) {
+  const size_t n = (size_t)p.n, rows = count * PB_BITS;
+  int8_t *X, *E, *E2;
+  int32_t* rowsum;
+  uint32_t* rkA;
+  LWE_CHECK(ensure_t(c, B_X, rows * p.ldx, &X));
+  LWE_CHECK(ensure_t(c, B_E, rows * n, &E));
+  LWE_CHECK(ensure_t(c, B_E2, count * PB_BITS, &E2));
+  LWE_CHECK(ensure_t(c, B_ROWSUM, rows * 4, &rowsum));
+  LWE_CHECK(ensure_t(c, B_RKA, 44 * 4, &rkA));
+  KLAUNCH("expand_keys", s, launch_expand_keys(pk_dev, 0, 1, c->d_T0, rkA, s));
+  // r_r (domain 1, Gaussian), e1_r (domain 2, Gaussian), e2 (domain 3, uniform)
+  PbSampleArgs sa;
+  memset(&sa, 0, sizeof(sa));
+  const size_t words[3] = {rows * n, rows * n, count * PB_BITS};
+  sa.dist[0] = 1;
+  sa.dist[1] = 1;
+  sa.dist[2] = 2;
+  sa.rowlen[0] = sa.rowlen[1] = p.n;
+  sa.rowlen[2] = PB_BITS;
+  sa.dst8[0] = X;
+  sa.inst_stride8[0] = (size_t)PB_BITS * p.ldx;
+  sa.ld8[0] = p.ldx;
+  sa.dst8[1] = E;
+  sa.inst_stride8[1] = (size_t)PB_BITS * n;
+  sa.ld8[1] = p.n;
+  sa.dst8[2] = E2;
+  sa.inst_stride8[2] = PB_BITS;
+  sa.ld8[2] = PB_BITS;
+  const size_t per_inst[3] = {words[0] / count, words[1] / count, words[2] / count};
+  LWE_CHECK(pb_noise(c, p, count, dcoins, 3, per_inst, sa, s));
+  // row sums of r (limb correction) and v_r
+  PbRowsArgs ra;
+  memset(&ra, 0, sizeof(ra));
+  ra.X = X;
+  ra.ldx = p.ldx;
+  ra.n = p.n;
+  ra.rows = (int)rows;
+  ra.rows_per_inst = PB_BITS;
+  ra.rowsum = rowsum;
+  ra.mode = ct_cmp ? 2 : 1;
+  ra.t = pk_dev + 16;
+  ra.coef_bytes = p.coef_bytes;
+  ra.e2 = E2;
+  ra.mu = mu_dev;
+  ra.mu_stride = mu_stride;
+  ra.q = p.q;
+  ra.out = ct_out;
+  ra.out_stride = p.ct_bytes;
+  ra.v_off = (size_t)p.coef_bytes * PB_BITS * n;
+  ra.cmp = ct_cmp;
+  ra.cmp_stride = p.ct_bytes;
+  ra.flags = flags;
+  KLAUNCH("pb_rows", s, launch_pb_rows(ra, s));
+  ProdArgs a = pb_prod_args(c, p);
+  a.rkA = rkA;
+  a.X = X;
+  a.M = (int)rows;
+  a.ncols = p.n;
+  a.mode = ct_cmp ? PM_COMPARE : PM_ENCRYPT;
+  a.E = E;
+  a.out = ct_out;
+  a.out_stride = p.ct_bytes;
+  a.cmp = ct_cmp;
+  a.cmp_stride = p.ct_bytes;
+  a.flags = flags;
+  a.rowsum = rowsum;
+  a.rows_per_inst = PB_BITS;
+  return run_product(c, pid, p, a, false, s);
+}
+
+int pb_keygen(lwe_ctx* c, int pid, const Params& p, size_t count, const uint8_t* seedA, const uint8_t* seedSK,
+              const uint8_t* z, uint8_t* pk, uint8_t* sk, void* stream) {
+  DevGuard g(c->device);
+  hipStream_t s = pick_stream(c, stream);
+  CALL_SCOPE(c, s);
+  const size_t n = (size_t)p.n;
+  const uint8_t *dA, *dS, *dZ;
+  LWE_CHECK(stage_in(c, B_SEEDA, seedA, count * 16, s, &dA));
+  LWE_CHECK(stage_in(c, B_SEEDSK, seedSK, count * 16, s, &dS));
+  LWE_CHECK(stage_in(c, B_Z, z, count * 32, s, &dZ));
+  OutStage opk, osk;
+  LWE_CHECK(stage_out(c, B_PK, pk, count * p.pk_bytes, opk));
+  LWE_CHECK(stage_out(c, B_SK, sk, count * p.sk_bytes, osk));
+  uint32_t* rkA;
+  int8_t *X, *E;
+  int32_t* rowsum;
+  LWE_CHECK(ensure_t(c, B_RKA, count * 44 * 4, &rkA));
+  LWE_CHECK(ensure_t(c, B_X, count * (size_t)p.ldx, &X));
+  LWE_CHECK(ensure_t(c, B_E, count * n, &E));
+  LWE_CHECK(ensure_t(c, B_ROWSUM, count * 4, &rowsum));
+  KLAUNCH("expand_keys", s, launch_expand_keys(dA, 16, (int)count, c->d_T0, rkA, s));
+  // s (domain 1, binomial; also as int16 at the start of sk), e (domain 2, Gaussian)
+  PbSampleArgs sa;
+  memset(&sa, 0, sizeof(sa));
+  const size_t words[3] = {n, n, 0};
+  sa.dist[0] = 0;
+  sa.dist[1] = 1;
+  sa.rowlen[0] = sa.rowlen[1] = p.n;
+  sa.dst8[0] = X;
+  sa.inst_stride8[0] = (size_t)p.ldx;
+  sa.ld8[0] = p.ldx;
+  sa.dst8[1] = E;
+  sa.inst_stride8[1] = n;
+  sa.ld8[1] = p.n;
+  sa.dst16 = osk.dev;
+  sa.dst16_stride = p.sk_bytes;
+  LWE_CHECK(pb_noise(c, p, count, dS, 2, words, sa, s));
+  PbRowsArgs ra;
+  memset(&ra, 0, sizeof(ra));
+  ra.X = X;
+  ra.ldx = p.ldx;
+  ra.n = p.n;
+  ra.rows = (int)count;
+  ra.rows_per_inst = 1;
+  ra.rowsum = rowsum;
+  KLAUNCH("pb_rows", s, launch_pb_rows(ra, s));
+  // t = A s + e mod q (every instance its own A)
+  ProdArgs a = pb_prod_args(c, p);
+  a.rkA = rkA;
+  a.X = X;
+  a.M = (int)count;
+  a.ncols = p.n;
+  a.per_inst_A = 1;
+  a.mode = PM_KEYGEN;
+  a.E = E;
+  a.out = opk.dev;
+  a.out_stride = p.pk_bytes;
+  a.out_off = 16;
+  a.rowsum = rowsum;
+  a.rows_per_inst = 1;
+  LWE_CHECK(run_product(c, pid, p, a, true, s));
+  // pk = seedA || t ; sk = s || pk || H(pk) || z
+  HIP_CHECK(hipMemcpy2DAsync(opk.dev, p.pk_bytes, dA, 16, 16, count, hipMemcpyDeviceToDevice, s));
+  const size_t off_pk = 2 * n, off_pkh = off_pk + p.pk_bytes, off_z = off_pkh + 32;
+  HIP_CHECK(hipMemcpy2DAsync(osk.dev + off_pk, p.sk_bytes, opk.dev, p.pk_bytes, p.pk_bytes, count,
+                             hipMemcpyDeviceToDevice, s));
+  HIP_CHECK(hipMemcpy2DAsync(osk.dev + off_z, p.sk_bytes, dZ, 32, 32, count, hipMemcpyDeviceToDevice, s));
+  std::vector<uint8_t> hpk(count * p.pk_bytes), hh(count * 32);
+  HIP_CHECK(hipMemcpyAsync(hpk.data(), opk.dev, hpk.size(), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  host_for(c->host_threads, count,
+           [&](size_t i) { sha3_256(hpk.data() + i * p.pk_bytes, p.pk_bytes, hh.data() + i * 32); });
+  uint8_t* dh;
+  LWE_CHECK(ensure_t(c, B_HCT, count * 32, &dh));
+  HIP_CHECK(hipMemcpyAsync(dh, hh.data(), hh.size(), hipMemcpyHostToDevice, s));
+  HIP_CHECK(hipMemcpy2DAsync(osk.dev + off_pkh, p.sk_bytes, dh, 32, 32, count, hipMemcpyDeviceToDevice, s));
+  LWE_CHECK(finish_out(opk, s));
+  LWE_CHECK(finish_out(osk, s));
+  HIP_CHECK(hipStreamSynchronize(s));  // hh must outlive the copy
+  return LWE_OK;
+}
+
+int pb_encaps(lwe_ctx* c, int pid, const Params& p, size_t count, const uint8_t* pk, const uint8_t* mu, uint8_t* ct,
+              uint8_t* ss, void* stream) {
+  DevGuard g(c->device);
+  hipStream_t s = pick_stream(c, stream);
+  CALL_SCOPE(c, s);
+  const size_t mb = p.mu_bytes;
+  std::vector<uint8_t> hpk, hmu;
+  LWE_CHECK(host_copy2(pk, p.pk_bytes, hpk, mu, count * mb, hmu, s));
+  uint8_t pkh[32];
+  host_pkh(c, hpk.data(), p.pk_bytes, pkh);
+  const uint8_t *dpk, *dmu;
+  LWE_CHECK(stage_in(c, B_PK, pk, p.pk_bytes, s, &dpk));
+  LWE_CHECK(stage_in(c, B_MU, mu, count * mb, s, &dmu));
+  OutStage oct;
+  LWE_CHECK(stage_out(c, B_CT, ct, count * p.ct_bytes, oct));
+  uint8_t* dcoins;
+  LWE_CHECK(ensure_t(c, B_COINS, count * 16, &dcoins));
+  std::vector<uint8_t> hcoins(count * 16), hkp(count * 32);
+  const uint8_t one = 1;
+  host_for(c->host_threads, count, [&](size_t i) {
+    uint8_t h[32];
+    sha3_256_3(&one, 1, pkh, 32, hmu.data() + i * mb, mb, h);
+    memcpy(hcoins.data() + i * 16, h, 16);
+    sha3_256_3(pkh, 32, hmu.data() + i * mb, mb, nullptr, 0, hkp.data() + i * 32);
+  });
+  HIP_CHECK(hipMemcpyAsync(dcoins, hcoins.data(), count * 16, hipMemcpyHostToDevice, s));
+  LWE_CHECK(pb_encrypt_core(c, pid, p, count, dpk, dcoins, dmu, mb, oct.dev, nullptr, nullptr, s));
+  std::vector<uint8_t> hct(count * p.ct_bytes), hss(count * 32);
+  HIP_CHECK(hipMemcpyAsync(hct.data(), oct.dev, hct.size(), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  host_for(c->host_threads, count, [&](size_t i) {
+    uint8_t h[32];
+    sha3_256(hct.data() + i * p.ct_bytes, p.ct_bytes, h);
+    sha3_256_3(hkp.data() + i * 32, 32, h, 32, nullptr, 0, hss.data() + i * 32);
+  });
+  if (oct.host) {
+    memcpy(ct, hct.data(), hct.size());
+    oct.bytes = 0;
+  }
+  if (is_device_ptr(ss)) {
+    HIP_CHECK(hipMemcpyAsync(ss, hss.data(), hss.size(), hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+  } else {
+    memcpy(ss, hss.data(), hss.size());
+  }
+  return LWE_OK;
+}
+
+int pb_decaps(lwe_ctx* c, int pid, const Params& p, size_t count, const uint8_t* sk, const uint8_t* ct, uint8_t* ss,
+              void* stream) {
+  DevGuard g(c->device);
+  hipStream_t s = pick_stream(c, stream);
+  CALL_SCOPE(c, s);
+  const size_t n = (size_t)p.n, mb = p.mu_bytes;
+  const size_t off_pk = 2 * n, off_pkh = off_pk + p.pk_bytes;
+  const uint8_t *dsk, *dct;
+  LWE_CHECK(stage_in(c, B_SK, sk, p.sk_bytes, s, &dsk));
+  LWE_CHECK(stage_in(c, B_CT, ct, count * p.ct_bytes, s, &dct));
+  uint8_t *dmu2, *dcoins;
+  uint32_t* dflags;
+  LWE_CHECK(ensure_t(c, B_MU2, count * mb, &dmu2));
+  LWE_CHECK(ensure_t(c, B_COINS, count * 16, &dcoins));
+  LWE_CHECK(ensure_t(c, B_FLAGS, count * 4, &dflags));
+  // m' = Decrypt(sk, ct) (Alg. 3)
+  PbDecArgs da;
+  da.ct = dct;
+  da.ct_stride = p.ct_bytes;
+  da.sk = dsk;
+  da.n = p.n;
+  da.q = p.q;
+  da.coef_bytes = p.coef_bytes;
+  da.count = (int)count;
+  da.mu_out = dmu2;
+  KLAUNCH("pb_decrypt", s, launch_pb_decrypt(da, s));
+  // coins' and K'' of m' on the host; the received ciphertexts come back in the same wait
+  std::vector<uint8_t> hmu(count * mb), tail(64), hct(count * p.ct_bytes);
+  HIP_CHECK(hipMemcpyAsync(hmu.data(), dmu2, hmu.size(), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipMemcpyAsync(tail.data(), dsk + off_pkh, 64, hipMemcpyDeviceToHost, s));
+  if (is_device_ptr(ct))
+    HIP_CHECK(hipMemcpyAsync(hct.data(), ct, hct.size(), hipMemcpyDeviceToHost, s));
+  else
+    memcpy(hct.data(), ct, hct.size());
+  HIP_CHECK(hipStreamSynchronize(s));
+  std::vector<uint8_t> hcoins(count * 16), hkp(count * 32), hhct(count * 32);
+  const uint8_t one = 1;
+  const uint8_t* pkh = tail.data();
+  host_for(c->host_threads, count, [&](size_t i) {
+    uint8_t h[32];
+    sha3_256_3(&one, 1, pkh, 32, hmu.data() + i * mb, mb, h);
+    memcpy(hcoins.data() + i * 16, h, 16);
+    sha3_256_3(pkh, 32, hmu.data() + i * mb, mb, nullptr, 0, hkp.data() + i * 32);
+  });
+  HIP_CHECK(hipMemcpyAsync(dcoins, hcoins.data(), count * 16, hipMemcpyHostToDevice, s));
+  KLAUNCH("fill", s, launch_fill_u32(dflags, count, 0, s));
+  // c' = Encrypt(pk, m'; coins') compared with c on the device
+  LWE_CHECK(pb_encrypt_core(c, pid, p, count, dsk + off_pk, dcoins, dmu2, mb, nullptr, dct, dflags, s));
+  std::vector<uint32_t> hflags(count);
+  HIP_CHECK(hipMemcpyAsync(hflags.data(), dflags, count * 4, hipMemcpyDeviceToHost, s));
+  // H(ct) on the host while the device re-encrypts
+  host_for(c->host_threads, count,
+           [&](size_t i) { sha3_256(hct.data() + i * p.ct_bytes, p.ct_bytes, hhct.data() + i * 32); });
+  HIP_CHECK(hipStreamSynchronize(s));
+  std::vector<uint8_t> hss(count * 32);
+  const uint8_t* zz = tail.data() + 32;
+  for (size_t i = 0; i < count; ++i) {
+    uint8_t buf[64];
+    const uint8_t rej = (uint8_t)(0u - (uint32_t)(hflags[i] != 0));
+    for (int k = 0; k < 32; ++k) buf[k] = (uint8_t)((hkp[i * 32 + k] & (uint8_t)~rej) | (zz[k] & rej));
+    memcpy(buf + 32, hhct.data() + i * 32, 32);
+    sha3_256(buf, 64, hss.data() + i * 32);
+  }
+  if (is_device_ptr(ss)) {
+    HIP_CHECK(hipMemcpyAsync(ss, hss.data(), hss.size(), hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+  } else {
+    memcpy(ss, hss.data(), hss.size());
+  }
+  return LWE_OK;
 }
 
 }  // namespace
@@ -656,6 +990,24 @@ size_t lwe_ctx_call_bytes(lwe_ctx* c, int pid, int op, size_t count) {
     if (pl.acc_bytes) b += r(pl.acc_bytes);
     return b;
   };
+  if (p->paper) {
+    // the paper's sets: stream product (split-K accumulator via product()), DRBG chains,
+    // operands of 256 rows per instance, row sums
+    const size_t rows = count * PB_BITS, n = (size_t)p->n;
+    const size_t req = (size_t)drbg_requests(rows / count * n);
+    const size_t enc = r(rows * p->ldx) + r(rows * n) + r(count * PB_BITS) + r(rows * 4) + r(44 * 4) +
+                       r(count * 3 * req * 256) + product((int)rows, p->n, false, false);
+    size_t b = 0;
+    if (op == 0)
+      b = r(count * 16) * 2 + r(count * 32) + r(count * p->pk_bytes) + r(count * p->sk_bytes) + r(count * 44 * 4) +
+          r(count * p->ldx) + r(count * n) + r(count * 4) + r(count * 2 * 256) + product((int)count, p->n, true, true) +
+          r(count * 32);
+    else if (op == 1)
+      b = r(p->pk_bytes) + r(count * mb) + r(count * p->ct_bytes) + r(count * 16) + enc;
+    else
+      b = r(p->sk_bytes) + r(count * p->ct_bytes) + r(count * mb) + r(count * 16) + r(count * 4) + enc;
+    return b + T0_BYTES;
+  }
   const size_t M = count * 8;
   // encrypt_core: S' (whole 16-row groups), E', E'', round keys of seedA
   const size_t enc = r((M + 15) / 16 * 16 * ldx) + r(M * n) + r(count * 64) + r(44 * 4) +
@@ -714,6 +1066,7 @@ int lwe_prof_read(lwe_ctx* c, const char* kernel, uint64_t* launches, double* to
 }
 
 int lwe_param_id(uint32_t n) { return find_param(n); }
+int lwe_param_id_paper(uint32_t n) { return find_param_paper(n); }
 
 int lwe_param_register(uint32_t n, uint32_t logq, uint32_t B, uint32_t K, double sigma) {
   return register_param(n, logq, B, K, sigma);
@@ -731,6 +1084,13 @@ int lwe_param_get(int pid, lwe_param_info* out) {
   out->sk_bytes = p->sk_bytes;
   out->ct_bytes = p->ct_bytes;
   out->mu_bytes = p->mu_bytes;
+  out->paper = (uint32_t)p->paper;
+  out->q = p->q;
+  out->nbar = (uint32_t)p->nbar;
+  out->mbar = (uint32_t)p->mbar;
+  out->coef_bytes = (uint32_t)p->coef_bytes;
+  out->eta = (uint32_t)p->eta;
+  out->k = (uint32_t)p->ku;
   return LWE_OK;
 }
 
@@ -787,6 +1147,7 @@ int lwe_keygen_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* seedA, co
   if (count == 0) return LWE_OK;
   if (!seedA || !seedSK || !z || !pk || !sk || count > LWE_MAX_BATCH) return LWE_EINVAL;
   const Params& p = *pp;
+  if (p.paper) return pb_keygen(c, pid, p, count, seedA, seedSK, z, pk, sk, stream);
   DevGuard g(c->device);
   hipStream_t s = pick_stream(c, stream);
   CALL_SCOPE(c, s);
@@ -884,6 +1245,7 @@ int lwe_encaps_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* pk, const
   if (count == 0) return LWE_OK;
   if (!pk || !mu || !ct || !ss || count > LWE_MAX_BATCH) return LWE_EINVAL;
   const Params& p = *pp;
+  if (p.paper) return pb_encaps(c, pid, p, count, pk, mu, ct, ss, stream);
   DevGuard g(c->device);
   hipStream_t s = pick_stream(c, stream);
   CALL_SCOPE(c, s);
@@ -974,6 +1336,7 @@ int lwe_decaps_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* sk, const
   if (count == 0) return LWE_OK;
   if (!sk || !ct || !ss || count > LWE_MAX_BATCH) return LWE_EINVAL;
   const Params& p = *pp;
+  if (p.paper) return pb_decaps(c, pid, p, count, sk, ct, ss, stream);
   DevGuard g(c->device);
   hipStream_t s = pick_stream(c, stream);
   CALL_SCOPE(c, s);
@@ -1099,6 +1462,7 @@ int lwe_test_expand_A(lwe_ctx* c, int pid, const uint8_t* seedA, uint32_t col0, 
   const Params* pp;
   if (!c || !seedA || !out) return LWE_EINVAL;
   LWE_CHECK(check_pid(pid, &pp));
+  if (pp->paper) return LWE_EUNSUPPORTED;
   const Params& p = *pp;
   if ((uint64_t)col0 + ncols > (uint64_t)p.n) return LWE_EINVAL;
   DevGuard g(c->device);
@@ -1141,6 +1505,7 @@ int lwe_test_sample(lwe_ctx* c, int pid, const uint8_t* key, uint32_t domain, ui
   const Params* pp;
   if (!c || !key || !out) return LWE_EINVAL;
   LWE_CHECK(check_pid(pid, &pp));
+  if (pp->paper) return LWE_EUNSUPPORTED;
   DevGuard g(c->device);
   hipStream_t s = pick_stream(c, stream);
   CALL_SCOPE(c, s);
@@ -1162,6 +1527,7 @@ int lwe_test_encrypt(lwe_ctx* c, int pid, size_t count, const uint8_t* pk, const
   const Params* pp;
   if (!c || !pk || !coins || !mu || !ct || count > LWE_MAX_BATCH) return LWE_EINVAL;
   LWE_CHECK(check_pid(pid, &pp));
+  if (pp->paper) return LWE_EUNSUPPORTED;
   if (count == 0) return LWE_OK;
   const Params& p = *pp;
   DevGuard g(c->device);
@@ -1187,6 +1553,7 @@ int lwe_test_decrypt(lwe_ctx* c, int pid, size_t count, const uint8_t* sk, const
   const Params* pp;
   if (!c || !sk || !ct || !mu || count > LWE_MAX_BATCH) return LWE_EINVAL;
   LWE_CHECK(check_pid(pid, &pp));
+  if (pp->paper) return LWE_EUNSUPPORTED;
   if (count == 0) return LWE_OK;
   const Params& p = *pp;
   DevGuard g(c->device);
@@ -1237,6 +1604,7 @@ int lwe_test_sample_batch(lwe_ctx* c, int pid, size_t count, int mode, int layou
   if ((mode != 0 && mode != 1) || (layout != 0 && layout != 1)) return LWE_EINVAL;
   if ((mode == 1) != (E2_out != nullptr) || (mode == 1 && X16_out)) return LWE_EINVAL;
   LWE_CHECK(check_pid(pid, &pp));
+  if (pp->paper) return LWE_EUNSUPPORTED;
   const Params& p = *pp;
   DevGuard g(c->device);
   hipStream_t s = pick_stream(c, stream);
@@ -1285,6 +1653,7 @@ int lwe_test_product(lwe_ctx* c, int pid, size_t count, const uint8_t* seedA, co
   if (!c || !seedA || !Bt || !S || !E || !E2 || !mu || !ct || count == 0 || count > LWE_MAX_BATCH)
     return LWE_EINVAL;
   LWE_CHECK(check_pid(pid, &pp));
+  if (pp->paper) return LWE_EUNSUPPORTED;
   const Params& p = *pp;
   DevGuard g(c->device);
   hipStream_t s = pick_stream(c, stream);
@@ -1435,6 +1804,7 @@ extern "C" int lwe_decaps_batch_noalloc(int pid, size_t count, const uint8_t* sk
     (void)hipGetLastError();
     return LWE_EDEVICE;
   }
+  if (pp->paper) return LWE_EUNSUPPORTED;
   uint8_t* base = nullptr;
   LWE_CHECK(noalloc_base(dev, &base));
   // A transient context over the arena: device hashing on the caller's stream only (no host

@@ -680,6 +680,50 @@ __device__ __forceinline__ void flag_tile(const ProdArgs& a, int row_base, uint3
     atomicOr(&a.flags[(row_base >> 3) + 1], (uint32_t)((bal >> 32) != 0));
 }
 
+// ---- the paper's sets (prime q) ----
+// x mod q for x < 2^64 (a multiple of q added first keeps negative sums non-negative)
+__device__ __forceinline__ uint32_t mod_q64(long long x, uint32_t q) {
+  long long r = x % (long long)q;
+  return (uint32_t)(r < 0 ? r + (long long)q : r);
+}
+
+// A[i][j] = word mod q for the two 16-bit words of w (both halves; none for q > 2^16)
+__device__ __forceinline__ uint32_t reduce_pair_q(uint32_t w, uint32_t q, uint32_t magic) {
+  if (!magic) return w;
+  const uint32_t x0 = w & 0xffffu, x1 = w >> 16;
+  const uint32_t r0 = x0 - q * __umulhi(x0, magic), r1 = x1 - q * __umulhi(x1, magic);
+  return r0 | (r1 << 16);
+}
+
+// Offset limbs of four values x < 2^16 held as 16-bit halves of a and b: the int8 bytes
+// lo - 128 and hi - 128 (the bytes of x with the top bit flipped).
+__device__ __forceinline__ void limbs4_offset(uint32_t a, uint32_t b, uint32_t& lo, uint32_t& hi) {
+  lo = __builtin_amdgcn_perm(b, a, 0x06040200u) ^ 0x80808080u;
+  hi = __builtin_amdgcn_perm(b, a, 0x07050301u) ^ 0x80808080u;
+}
+
+// Finalises element (row, col) of a paper-set product: D holds sums of limb partials already
+// reduced mod q; adds the limb offsets' correction, the error and reduces mod q; stores the
+// coefficient (keygen: t at out_off of the pk record; encryption: u_r[col] of the ct record),
+// or in compare mode returns 1 if it differs from the received one.
+__device__ __forceinline__ uint32_t epi_store_prime(const ProdArgs& a, int row, int col, uint32_t D) {
+  const int inst = row / a.rows_per_inst, r = row - inst * a.rows_per_inst;
+  const long long v = (long long)D + 32896LL * a.rowsum[row] + (long long)a.E[(size_t)row * a.n + col];
+  const uint32_t val = mod_q64(v, a.qp);
+  const size_t off = a.out_off + (size_t)a.coef_bytes * ((size_t)r * a.n + col);
+  if (a.mode == PM_COMPARE) {
+    const uint8_t* src = a.cmp + (size_t)inst * a.cmp_stride + off;
+    const uint32_t got = a.coef_bytes == 4 ? *(const uint32_t*)src : (uint32_t)*(const uint16_t*)src;
+    return got != val ? 1u : 0u;
+  }
+  uint8_t* dst = a.out + (size_t)inst * a.out_stride + off;
+  if (a.coef_bytes == 4)
+    *(uint32_t*)dst = val;
+  else
+    *(uint16_t*)dst = (uint16_t)val;
+  return 0u;
+}
+
 // ======================================================================================
 // Product, streaming form (small row counts: plain encryption, all key generations).
 // Each wave generates its own A fragments per 64-row contraction step and multiplies them
@@ -687,7 +731,8 @@ __device__ __forceinline__ void flag_tile(const ProdArgs& a, int row_base, uint3
 //   grid.x = n_jt * n_kc, grid.y = row tiles (or instances when per_inst_A)
 // ======================================================================================
 // MAT: read A from the expanded copy a.Amat instead of regenerating it (unfused variant).
-template <int CG, int RG, bool TRANS, bool MAT>
+// PRIME: the paper's sets (A mod a prime q, offset limbs, exact reduction mod q).
+template <int CG, int RG, bool TRANS, bool MAT, bool PRIME = false>
 __global__ void __launch_bounds__(1024) k_prod_stream(ProdArgs a, int ks_per_wave) {
   // Lane-replicated T-tables in static LDS (64 KB, conflict-free lookups; none in the unfused
   // variant); the reduction / transpose scratch in dynamic LDS.
@@ -767,7 +812,13 @@ __global__ void __launch_bounds__(1024) k_prod_stream(ProdArgs a, int ks_per_wav
         }
         uint32_t lo[4], hi[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) limbs4(w[2 * q] & qmask2, w[2 * q + 1] & qmask2, lo[q], hi[q]);
+        for (int q = 0; q < 4; ++q) {
+          if constexpr (PRIME)
+            limbs4_offset(reduce_pair_q(w[2 * q], a.qp, a.qp_magic), reduce_pair_q(w[2 * q + 1], a.qp, a.qp_magic),
+                          lo[q], hi[q]);
+          else
+            limbs4(w[2 * q] & qmask2, w[2 * q + 1] & qmask2, lo[q], hi[q]);
+        }
         yf[cg][0] = v4i{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3]};
         yf[cg][1] = v4i{(int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
       }
@@ -797,7 +848,13 @@ __global__ void __launch_bounds__(1024) k_prod_stream(ProdArgs a, int ks_per_wav
         }
         uint32_t lo[4], hi[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) limbs4(w[2 * q] & qmask2, w[2 * q + 1] & qmask2, lo[q], hi[q]);
+        for (int q = 0; q < 4; ++q) {
+          if constexpr (PRIME)
+            limbs4_offset(reduce_pair_q(w[2 * q], a.qp, a.qp_magic), reduce_pair_q(w[2 * q + 1], a.qp, a.qp_magic),
+                          lo[q], hi[q]);
+          else
+            limbs4(w[2 * q] & qmask2, w[2 * q + 1] & qmask2, lo[q], hi[q]);
+        }
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           my[(0 * CG + cg) * 1024 + r * 64 + lane] = (uint8_t)(lo[r >> 2] >> (8 * (r & 3)));
@@ -830,8 +887,12 @@ __global__ void __launch_bounds__(1024) k_prod_stream(ProdArgs a, int ks_per_wav
 #pragma unroll
     for (int cg = 0; cg < CG; ++cg)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-        D[rg][cg][i] = (uint32_t)acc[rg][cg][0][i] + ((uint32_t)acc[rg][cg][1][i] << 8);
+      for (int i = 0; i < 4; ++i) {
+        if constexpr (PRIME)
+          D[rg][cg][i] = mod_q64((long long)acc[rg][cg][0][i] + 256LL * acc[rg][cg][1][i], a.qp);
+        else
+          D[rg][cg][i] = (uint32_t)acc[rg][cg][0][i] + ((uint32_t)acc[rg][cg][1][i] << 8);
+      }
   if (W > 1) {
 #pragma unroll
     for (int rg = 0; rg < RG; ++rg)
@@ -864,10 +925,20 @@ __global__ void __launch_bounds__(1024) k_prod_stream(ProdArgs a, int ks_per_wav
         if (row >= m_end || col >= a.ncols) continue;
         if (a.n_kc > 1)
           atomicAdd((uint32_t*)&a.acc32[(size_t)row * a.acc_ld + col], D[rg][cg][i]);
+        else if constexpr (PRIME)
+          mism |= epi_store_prime(a, row, col, D[rg][cg][i]);
         else
           mism |= epi_store(a, row, col, D[rg][cg][i]);
       }
-    if (a.mode == PM_COMPARE && a.n_kc == 1) flag_tile(a, row_base, mism);
+    if (a.mode == PM_COMPARE && a.n_kc == 1) {
+      if constexpr (PRIME) {
+        // rows_per_inst (256) is a multiple of 16: the tile's rows belong to one instance
+        if (__ballot(mism != 0) && (threadIdx.x & 63) == 0 && row_base < m_end)
+          atomicOr(&a.flags[row_base / a.rows_per_inst], 1u);
+      } else {
+        flag_tile(a, row_base, mism);
+      }
+    }
   }
 }
 
@@ -1215,6 +1286,12 @@ __global__ void k_finalize(ProdArgs a) {
   const bool valid = t < total;
   const int row = valid ? (int)(t / a.ncols) : 0, col = valid ? (int)(t % a.ncols) : 0;
   uint32_t mism = 0;
+  if (a.qp) {
+    // the paper's sets: one flag update per differing element (rows_per_inst rows per instance)
+    if (valid) mism = epi_store_prime(a, row, col, (uint32_t)a.acc32[(size_t)row * a.acc_ld + col]);
+    if (a.mode == PM_COMPARE && mism) atomicOr(&a.flags[row / a.rows_per_inst], 1u);
+    return;
+  }
   if (valid) mism = epi_store(a, row, col, (uint32_t)a.acc32[(size_t)row * a.acc_ld + col]);
   if (a.mode == PM_COMPARE) {
     // a wave covers at most two instances (ncols >= 16 and 8 rows per instance)
@@ -1538,7 +1615,7 @@ __device__ __forceinline__ uint32_t interleave_in(uint32_t w, uint32_t sel) {
 // its CU with the product and sampler workgroups of other streams, and must leave them room.
 // ALIGNED: every record starts at a 4-byte boundary (whole-word loads).
 template <bool ALIGNED>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
 k_hash_records(int count, const uint8_t* __restrict__ in, size_t stride, size_t len, uint8_t* out) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t p = (uint32_t)(t & 1);
@@ -1818,10 +1895,14 @@ static hipError_t launch_stream_t(const ProdArgs& a, int waves, int n_row_tiles,
   const size_t lds = (size_t)waves * RG * CG * 256 * 4 + (TRANS ? (size_t)waves * 2 * CG * 1024 : 0);
   if (lds > STREAM_DYN_LDS) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(a.n_jt * a.n_kc), (unsigned)n_row_tiles);
-  if (a.Amat)
+  if (a.qp) {
+    if (a.Amat) return hipErrorInvalidValue;  // the paper's sets regenerate A (fused) only
+    hipLaunchKernelGGL((k_prod_stream<CG, RG, TRANS, false, true>), grid, dim3(64 * waves), lds, s, a, ks);
+  } else if (a.Amat) {
     hipLaunchKernelGGL((k_prod_stream<CG, RG, TRANS, true>), grid, dim3(64 * waves), lds, s, a, ks);
-  else
+  } else {
     hipLaunchKernelGGL((k_prod_stream<CG, RG, TRANS, false>), grid, dim3(64 * waves), lds, s, a, ks);
+  }
   return hipGetLastError();
 }
 
@@ -1965,6 +2046,9 @@ template <int CG, int RG, bool TR>
 static hipError_t allow_lds_stream() {
   hipError_t e = hipFuncSetAttribute((const void*)k_prod_stream<CG, RG, TR, false>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)STREAM_DYN_LDS);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_prod_stream<CG, RG, TR, false, true>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)STREAM_DYN_LDS);
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)k_prod_stream<CG, RG, TR, true>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)STREAM_DYN_LDS);

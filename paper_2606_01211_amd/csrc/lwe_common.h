@@ -17,6 +17,9 @@ constexpr int MBAR = 8;
 constexpr int MAX_K = 15;        // largest CDF support handled by the sampler
 constexpr int SHA3_RATE = 136;   // SHA3-256 rate in bytes
 
+constexpr int PB_BITS = 256;      // the paper's sets: one encryption per message bit
+constexpr int DRBG_REQ_BLOCKS = 4096;  // AES blocks per CTR_DRBG Generate request (2^19 bits)
+
 // One registered parameter set.  T[0..K] is the 16-bit CDF table of the error
 // distribution; the sampler compares 15 keystream bits against T[0..K-1].
 struct Params {
@@ -25,6 +28,15 @@ struct Params {
   uint16_t T[MAX_K + 1];
   size_t pk_bytes, sk_bytes, ct_bytes, mu_bytes;
   int ldx;   // row stride in bytes of the int8 operand matrices (n rounded up to 64)
+  // 0: matrix form (nbar = mbar = 8, q = 2^logq, CDF noise from AES-128-CTR).
+  // 1: the paper's own sets (Table 1): nbar = 1, mbar = 256 (one encryption per message bit,
+  //    one bit per coefficient), prime q, s binomial(eta), e / r / e1 Gaussian (CDF table),
+  //    e2 uniform on [-ku, ku], all noise from the AES-256 CTR_DRBG.
+  int paper;
+  uint32_t q;       // modulus
+  int nbar, mbar;   // rows of S^T (columns of B), rows of B' per instance
+  int coef_bytes;   // bytes per serialised coefficient: 2, or 4 when q > 2^16
+  int eta, ku;      // paper sets: binomial parameter of s, bound of e2
 };
 
 // ------------------------------------------------------------------------------------

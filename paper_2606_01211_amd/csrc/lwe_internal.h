@@ -12,6 +12,7 @@ bool build_cdf(int K, double sigma, uint16_t* T);
 void finish_params(Params& p);
 const Params* get_params(int pid);
 int find_param(uint32_t n);
+int find_param_paper(uint32_t n);
 int register_param(uint32_t n, uint32_t logq, uint32_t B, uint32_t K, double sigma);
 const uint32_t* aes_T0();
 const uint8_t* aes_sbox();
@@ -62,6 +63,14 @@ struct ProdArgs {
   // Unfused variant: A already expanded into device memory, column-major [n][n] uint16
   // (A[i][j] at Amat[j * n + i], masked to logq bits); null when the product regenerates A.
   const uint16_t* Amat;
+  // The paper's sets (prime q; qp == 0 for the power-of-two sets).  A[i][j] = word mod qp, split
+  // into offset limbs x = (lo - 128) + 256 (hi - 128) + 32896 with lo, hi the bytes of x, so
+  // the epilogue adds 32896 * rowsum[row] (the row sums of X) and reduces mod qp exactly.
+  uint32_t qp;
+  uint32_t qp_magic;     // floor(2^32 / qp) + 1 for qp < 2^16 (16-bit words reduced), else 0
+  const int32_t* rowsum; // [M]
+  int rows_per_inst;     // output rows per instance (nbar for keygen, mbar for encryption)
+  int coef_bytes;        // bytes per stored coefficient
 };
 
 struct SampleArgs {
@@ -87,6 +96,61 @@ struct DecArgs {
   int mu_bytes;
   uint8_t* mu_out;       // [count][mu_bytes]
 };
+
+// ---- the paper's sets (kernels_paper.hip) ----
+struct PbChainArgs {
+  int nseg, rmax;         // noise streams per instance; request slots per stream in `chain`
+  uint32_t domain[3];     // domain number of each stream
+  int requests[3];        // Generate requests (4096 blocks each) per stream
+};
+
+struct PbSampleArgs {
+  int count, nseg, rmax;
+  uint32_t blocks[3];     // output blocks (8 words) per stream and instance
+  int dist[3];            // 0 binomial(eta), 1 CDF table, 2 uniform on [-ku, ku]
+  int rowlen[3];          // words per destination row (a multiple of 8)
+  int8_t* dst8[3];        // destination of stream s: instance i, row r, column c at
+  size_t inst_stride8[3]; //   dst8[s] + i * inst_stride8[s] + r * ld8[s] + c
+  int ld8[3];
+  uint8_t* dst16;         // optional int16 copy of stream 0 (sk records), may be null
+  size_t dst16_stride;
+  int eta, ku, K;
+  uint16_t T[MAX_K + 1];  // CDF table
+};
+
+struct PbRowsArgs {
+  const int8_t* X;        // [rows][ldx]
+  int ldx, n, rows, rows_per_inst;
+  int32_t* rowsum;        // [rows]
+  int mode;               // 0 row sums only; 1 and v_r stored; 2 and v_r compared
+  const uint8_t* t;       // t coefficients of the public key (coef_bytes each)
+  int coef_bytes;
+  const int8_t* e2;       // [count][rows_per_inst]
+  const uint8_t* mu;      // [count][mu_stride]
+  size_t mu_stride;
+  uint32_t q;
+  uint8_t* out;           // ct records: v_r at out + inst * out_stride + v_off + r * coef_bytes
+  size_t out_stride, v_off;
+  const uint8_t* cmp;     // compare mode: received ct records
+  size_t cmp_stride;
+  uint32_t* flags;        // compare mode: per instance, nonzero if any coefficient differs
+};
+
+struct PbDecArgs {
+  const uint8_t* ct;      // [count][ct_stride]: u_0..u_255 then v
+  size_t ct_stride;
+  const uint8_t* sk;      // s as n int16 at the start of the secret key
+  int n;
+  uint32_t q;
+  int coef_bytes, count;
+  uint8_t* mu_out;        // [count][32]
+};
+
+hipError_t launch_drbg_chain(const uint8_t* keys, size_t key_stride, int count, const PbChainArgs& a,
+                             const uint32_t* T0, uint32_t* chain, hipStream_t s);
+hipError_t launch_pb_sample(const PbSampleArgs& a, const uint32_t* T0, const uint32_t* chain, hipStream_t s);
+hipError_t launch_pb_rows(const PbRowsArgs& a, hipStream_t s);
+hipError_t launch_pb_decrypt(const PbDecArgs& a, hipStream_t s);
 
 // ---- launchers (kernels.hip); all return hipError_t of the launch ----
 hipError_t launch_fill_u32(uint32_t* p, size_t count, uint32_t v, hipStream_t s);

@@ -57,16 +57,57 @@ static std::deque<Params>& registry() {
       finish_params(p);
       reg.push_back(p);
     }
+    // The paper's own sets, Table 1: n, prime q, sigma of e / r / e1, k of e2 (eta = 3 for s).
+    // The Gaussian's support is the largest K whose 15-bit table stays strictly increasing.
+    const struct { int n; uint32_t q; double sigma; int ku; } table1[] = {
+        {512, 3329, 2.3, 3},    {1024, 12289, 2.3, 3}, {2048, 12289, 2.3, 3}, {4096, 12289, 1.7, 3},
+        {8192, 65537, 1.2, 2},  {16384, 65537, 1.2, 2}, {32768, 65537, 1.0, 2},
+    };
+    for (const auto& b : table1) {
+      Params p;
+      memset(&p, 0, sizeof(p));
+      p.paper = 1;
+      p.n = b.n;
+      p.q = b.q;
+      p.sigma = b.sigma;
+      p.ku = b.ku;
+      p.eta = 3;
+      p.B = 1;
+      for (int K = 1; K <= MAX_K; ++K) {
+        uint16_t T[MAX_K + 1];
+        if (build_cdf(K, p.sigma, T)) p.K = K;
+      }
+      build_cdf(p.K, p.sigma, p.T);
+      int bits = 0;
+      while ((1u << bits) < p.q) ++bits;
+      p.logq = bits;  // informational: bits of q
+      finish_params(p);
+      reg.push_back(p);
+    }
   }
   return reg;
 }
 
 void finish_params(Params& p) {
+  p.ldx = (p.n + 63) / 64 * 64;
+  if (p.paper) {
+    p.nbar = 1;
+    p.mbar = PB_BITS;
+    p.coef_bytes = p.q > 65536 ? 4 : 2;
+    p.pk_bytes = 16 + (size_t)p.n * p.coef_bytes;
+    p.sk_bytes = 2 * (size_t)p.n + p.pk_bytes + 64;
+    p.ct_bytes = (size_t)PB_BITS * ((size_t)p.n + 1) * p.coef_bytes;
+    p.mu_bytes = PB_BITS / 8;
+    return;
+  }
+  p.q = 1u << p.logq;
+  p.nbar = NBAR;
+  p.mbar = MBAR;
+  p.coef_bytes = 2;
   p.pk_bytes = 16 + (size_t)NBAR * p.n * 2;
   p.sk_bytes = (size_t)NBAR * p.n * 2 + p.pk_bytes + 64;
   p.ct_bytes = (size_t)MBAR * p.n * 2 + (size_t)MBAR * NBAR * 2;
   p.mu_bytes = (size_t)MBAR * NBAR * p.B / 8;
-  p.ldx = (p.n + 63) / 64 * 64;
 }
 
 const Params* get_params(int pid) {
@@ -80,7 +121,15 @@ int find_param(uint32_t n) {
   std::lock_guard<std::mutex> g(g_reg_mu);
   auto& reg = registry();
   for (size_t k = 0; k < reg.size(); ++k)
-    if (reg[k].n == (int)n) return (int)k;
+    if (!reg[k].paper && reg[k].n == (int)n) return (int)k;
+  return LWE_EINVAL;
+}
+
+int find_param_paper(uint32_t n) {
+  std::lock_guard<std::mutex> g(g_reg_mu);
+  auto& reg = registry();
+  for (size_t k = 0; k < reg.size(); ++k)
+    if (reg[k].paper && reg[k].n == (int)n) return (int)k;
   return LWE_EINVAL;
 }
 
@@ -101,7 +150,7 @@ int register_param(uint32_t n, uint32_t logq, uint32_t B, uint32_t K, double sig
   auto& reg = registry();
   for (size_t k = 0; k < reg.size(); ++k) {
     const Params& r = reg[k];
-    if (r.n == p.n && r.logq == p.logq && r.B == p.B && r.K == p.K && r.sigma == p.sigma)
+    if (!r.paper && r.n == p.n && r.logq == p.logq && r.B == p.B && r.K == p.K && r.sigma == p.sigma)
       return (int)k;
   }
   if (reg.size() >= 256) return LWE_ENOMEM;

@@ -26,7 +26,7 @@ EXPORTS = [
     "lwe_ctx_create", "lwe_ctx_destroy", "lwe_ctx_device_bytes", "lwe_ctx_set_budget", "lwe_ctx_trim",
     "lwe_ctx_call_bytes", "lwe_ctx_stream",
     "lwe_ctx_set_side_stream", "lwe_ctx_set_hash_lanes", "lwe_strerror",
-    "lwe_param_id", "lwe_param_register", "lwe_param_get", "lwe_pk_bytes", "lwe_sk_bytes",
+    "lwe_param_id", "lwe_param_id_paper", "lwe_param_register", "lwe_param_get", "lwe_pk_bytes", "lwe_sk_bytes",
     "lwe_ct_bytes", "lwe_mu_bytes", "lwe_cdf_table",
     "lwe_keygen", "lwe_encaps", "lwe_decaps",
     "lwe_keygen_rand", "lwe_encaps_rand",
@@ -38,7 +38,8 @@ EXPORTS = [
 ]
 
 KERNELS = ["sample", "prod_strip", "prod_strip_cmp", "prod_stream", "finalize", "decrypt", "fo_coins", "expand_keys",
-           "hash_records", "final_ss", "fill", "keystream", "sample_stream", "expand_A"]
+           "hash_records", "final_ss", "fill", "keystream", "sample_stream", "expand_A", "drbg_chain", "pb_sample",
+           "pb_rows", "pb_decrypt"]
 
 
 class LweLibraryMissing(ImportError):
@@ -56,6 +57,8 @@ class ParamInfo(C.Structure):
         ("n", C.c_uint32), ("logq", C.c_uint32), ("B", C.c_uint32), ("K", C.c_uint32),
         ("sigma", C.c_double), ("pk_bytes", C.c_size_t), ("sk_bytes", C.c_size_t),
         ("ct_bytes", C.c_size_t), ("mu_bytes", C.c_size_t),
+        ("paper", C.c_uint32), ("q", C.c_uint32), ("nbar", C.c_uint32), ("mbar", C.c_uint32),
+        ("coef_bytes", C.c_uint32), ("eta", C.c_uint32), ("k", C.c_uint32),
     ]
 
 
@@ -99,6 +102,7 @@ def lib() -> C.CDLL:
         "lwe_ctx_set_hash_lanes": (i32, [vp, i32]),
         "lwe_strerror": (C.c_char_p, [i32]),
         "lwe_param_id": (i32, [u32]),
+        "lwe_param_id_paper": (i32, [u32]),
         "lwe_param_register": (i32, [u32, u32, u32, u32, C.c_double]),
         "lwe_param_get": (i32, [i32, C.POINTER(ParamInfo)]),
         "lwe_pk_bytes": (sz, [i32]),
@@ -159,12 +163,27 @@ class Params:
     sk_bytes: int
     ct_bytes: int
     mu_bytes: int
+    paper: int = 0       # 1 for the paper's own sets (Table 1)
+    q: int = 0
+    nbar: int = 8
+    mbar: int = 8
+    coef_bytes: int = 2
+    eta: int = 0
+    k: int = 0
 
 
 def param_id(n: int) -> int:
     pid = lib().lwe_param_id(n)
     if pid < 0:
         raise KeyError("no parameter set for n=%d" % n)
+    return pid
+
+
+def param_id_paper(n: int) -> int:
+    """Id of the paper's own set for n (Table 1: one encryption per message bit, prime q)."""
+    pid = lib().lwe_param_id_paper(n)
+    if pid < 0:
+        raise KeyError("no Table 1 parameter set for n=%d" % n)
     return pid
 
 
@@ -178,7 +197,8 @@ def params(pid: int) -> Params:
     info = ParamInfo()
     _check(lib().lwe_param_get(pid, C.byref(info)), "lwe_param_get")
     return Params(pid, info.n, info.logq, info.B, info.K, info.sigma, info.pk_bytes,
-                  info.sk_bytes, info.ct_bytes, info.mu_bytes)
+                  info.sk_bytes, info.ct_bytes, info.mu_bytes, info.paper, info.q, info.nbar, info.mbar,
+                  info.coef_bytes, info.eta, info.k)
 
 
 def cdf_table(pid: int) -> np.ndarray:

@@ -29,3 +29,19 @@ def test_tuning_table_uses_built_shapes():
         assert t["m_chunks"] >= 1, n
         assert t.get("a_source", 0) in (0, 1), n
         assert tune.lds_fits(t["col_groups"], int(n)), n
+
+
+def test_lane_count_divides_the_timed_steps():
+    """Every lane runs the same number of timed steps: 20 steps on at most 14 lanes use 10
+    lanes of two steps, on 20 lanes (the default) one step each; 140 steps 14 or 20 lanes."""
+    sys.path.insert(0, ROOT)
+    import bench
+
+    assert bench.pick_lanes(20, 14) == (10, True)
+    assert bench.pick_lanes(140, 14) == (14, True)
+    assert bench.pick_lanes(20, 20) == (20, True)
+    assert bench.pick_lanes(140, 20) == (20, True)
+    assert bench.pick_lanes(5, 14) == (5, True)
+    assert bench.pick_lanes(1, 14) == (1, True)
+    s, even = bench.pick_lanes(17, 14)
+    assert s == 14 and not even
