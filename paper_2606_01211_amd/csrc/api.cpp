@@ -63,6 +63,11 @@ struct lwe_ctx {
   // cache of the last public key hashed on the host
   std::vector<uint8_t> pk_cache;
   uint8_t pkh_cache[32];
+  // Pinned host staging of the host hashing paths (public keys down, their hashes up), so that
+  // those copies are plain asynchronous transfers rather than the runtime's staged pageable
+  // copies, which serialise the host threads of concurrent contexts.  Grown on demand.
+  uint8_t* hpin = nullptr;
+  size_t hpin_cap = 0;
   lwe_tuning tuning[256];
   int host_threads = 1;
   // kernel timing (lwe_prof_*): events bracketing each launch, resolved lazily
@@ -204,6 +209,29 @@ int host_copy2(const void* a, size_t na, std::vector<uint8_t>& oa, const void* b
     memcpy(ob.data(), b, nb);
   }
   if (wait) HIP_CHECK(hipStreamSynchronize(s));
+  return LWE_OK;
+}
+
+// The context's pinned staging, at least `bytes`.  The host writes into it only after a wait
+// on the calling stream (which the call scope orders after every earlier call of the
+// context), so no queued copy still reads what it overwrites; growing it waits the same way.
+int host_pinned(lwe_ctx* c, size_t bytes, hipStream_t s, uint8_t** out) {
+  if (c->hpin_cap < bytes) {
+    const size_t want = (std::max(bytes, 2 * c->hpin_cap) + 4095) & ~(size_t)4095;
+    if (c->hpin) {
+      HIP_CHECK(hipStreamSynchronize(s));
+      (void)hipHostFree(c->hpin);
+      c->hpin = nullptr;
+      c->hpin_cap = 0;
+    }
+    if (hipHostMalloc((void**)&c->hpin, want, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      c->hpin = nullptr;
+      return LWE_ENOMEM;
+    }
+    c->hpin_cap = want;
+  }
+  *out = c->hpin;
   return LWE_OK;
 }
 
@@ -929,6 +957,7 @@ void lwe_ctx_destroy(lwe_ctx* c) {
   }
   if (c->own) (void)hipStreamSynchronize(c->own);
   if (c->d_T0) (void)hipFree(c->d_T0);
+  if (c->hpin) (void)hipHostFree(c->hpin);
   for (auto& r : c->prof_pending) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -1206,16 +1235,21 @@ int lwe_keygen_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* seedA, co
                              hipMemcpyDeviceToDevice, s));
   HIP_CHECK(hipMemcpy2DAsync(osk.dev + off_z, p.sk_bytes, dZ, 32, 32, count, hipMemcpyDeviceToDevice, s));
   if (use_host_hash(c, pid, count)) {
-    std::vector<uint8_t> hpk(count * p.pk_bytes), hh(count * 32);
-    HIP_CHECK(hipMemcpyAsync(hpk.data(), opk.dev, hpk.size(), hipMemcpyDeviceToHost, s));
+    // public keys down and their hashes up through the pinned staging; no wait after the
+    // upload (the staging is next written after a later wait on this context's stream)
+    uint8_t* hpk;
+    LWE_CHECK(host_pinned(c, count * (p.pk_bytes + 32), s, &hpk));
+    uint8_t* hh = hpk + count * p.pk_bytes;
+    HIP_CHECK(hipMemcpyAsync(hpk, opk.dev, count * p.pk_bytes, hipMemcpyDeviceToHost, s));
     HIP_CHECK(hipStreamSynchronize(s));
-    host_for(c->host_threads, count,
-             [&](size_t i) { sha3_256(hpk.data() + i * p.pk_bytes, p.pk_bytes, hh.data() + i * 32); });
+    host_for(c->host_threads, count, [&](size_t i) { sha3_256(hpk + i * p.pk_bytes, p.pk_bytes, hh + i * 32); });
+    // an encapsulation against the newest key finds its hash in the cache
+    c->pk_cache.assign(hpk + (count - 1) * p.pk_bytes, hpk + count * p.pk_bytes);
+    memcpy(c->pkh_cache, hh + (count - 1) * 32, 32);
     uint8_t* dh;
     LWE_CHECK(ensure_t(c, B_HCT, count * 32, &dh));
-    HIP_CHECK(hipMemcpyAsync(dh, hh.data(), hh.size(), hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipMemcpyAsync(dh, hh, count * 32, hipMemcpyHostToDevice, s));
     HIP_CHECK(hipMemcpy2DAsync(osk.dev + off_pkh, p.sk_bytes, dh, 32, 32, count, hipMemcpyDeviceToDevice, s));
-    HIP_CHECK(hipStreamSynchronize(s));  // hh must outlive the copy
   } else {
     uint8_t* dh;
     LWE_CHECK(ensure_t(c, B_HCT, count * 32, &dh));
@@ -1254,12 +1288,23 @@ int lwe_encaps_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* pk, const
   // same wait
   const bool hh = use_host_hash(c, pid, count);
   std::vector<uint8_t> hpk, hmu;
-  if (hh)
-    LWE_CHECK(host_copy2(pk, p.pk_bytes, hpk, mu, count * mb, hmu, s));
-  else
-    LWE_CHECK(host_copy(pk, p.pk_bytes, s, hpk));
   uint8_t pkh[32];
-  host_pkh(c, hpk.data(), p.pk_bytes, pkh);
+  const uint8_t* pkh_src = pkh;  // host source of the H(pk) upload (device hashing only)
+  if (hh) {
+    LWE_CHECK(host_copy2(pk, p.pk_bytes, hpk, mu, count * mb, hmu, s));
+    host_pkh(c, hpk.data(), p.pk_bytes, pkh);
+  } else if (is_device_ptr(pk)) {
+    // the key down and its hash up through the pinned staging
+    uint8_t* st;
+    LWE_CHECK(host_pinned(c, p.pk_bytes + 32, s, &st));
+    HIP_CHECK(hipMemcpyAsync(st, pk, p.pk_bytes, hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    host_pkh(c, st, p.pk_bytes, st + p.pk_bytes);
+    memcpy(pkh, st + p.pk_bytes, 32);
+    pkh_src = st + p.pk_bytes;
+  } else {
+    host_pkh(c, pk, p.pk_bytes, pkh);
+  }
   const uint8_t *dpk, *dmu;
   LWE_CHECK(stage_in(c, B_PK, pk, p.pk_bytes, s, &dpk));
   LWE_CHECK(stage_in(c, B_MU, mu, count * mb, s, &dmu));
@@ -1286,7 +1331,7 @@ int lwe_encaps_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* pk, const
   } else {
     uint8_t* dpkh;
     LWE_CHECK(ensure_t(c, B_PKH, 32, &dpkh));
-    HIP_CHECK(hipMemcpyAsync(dpkh, pkh, 32, hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipMemcpyAsync(dpkh, pkh_src, 32, hipMemcpyHostToDevice, s));
     KLAUNCH("fo_coins", s, launch_fo_coins((int)count, dpkh, dmu, mb, (int)mb, dcoins, dkp, s));
   }
   KLAUNCH("expand_keys", s, launch_expand_keys(dcoins, 16, (int)count, c->d_T0, drk, s));

@@ -33,6 +33,8 @@ import numpy as np
 
 KEYGEN, ENCAPS, DECAPS = 0, 1, 2
 OP_NAMES = {KEYGEN: "keygen", ENCAPS: "encaps", DECAPS: "decaps"}
+# group sizes whose exact footprint the library backend tabulates when it starts
+CALL_BYTES_TABLE = 4096
 
 
 @dataclass
@@ -273,19 +275,27 @@ class Server:
                     self._cv.wait(timeout=0.05)
                 (op, n, key), reqs, cap, trim = g
                 lane = self._free_lanes.pop()
-                if trim:
-                    self._trim_lane(lane)
-                    cap = max(cap, self._commit[lane])
-                self.backend.limit_lane(lane, cap)
-                self._reserved += cap - self._commit[lane]
-                self._commit[lane] = cap
+                # The lane's worker trims it and sets its cap: no backend call here, under the
+                # lock (a foreign call may wait a whole switch interval for the interpreter
+                # lock, and every dispatch would wait with it).  Until the worker has trimmed
+                # the lane it still holds what it held, so the reservation covers both.
+                res = max(cap, self._commit[lane]) if trim else cap
+                self._reserved += res - self._commit[lane]
+                self._commit[lane] = res
                 self._in_flight += 1
                 self.max_reserved = max(self.max_reserved, self._reserved)
                 self.max_in_flight_groups = max(self.max_in_flight_groups, self._in_flight)
                 self.groups.append((op, n, key, len(reqs)))
-            self._pool.submit(self._run_group, lane, op, n, key, reqs)
+                if trim:
+                    self.trims += 1
+            self._pool.submit(self._run_group, lane, op, n, key, reqs, cap, trim)
 
-    def _run_group(self, lane: int, op: int, n: int, key: int, reqs: List[Request]) -> None:
+    def _run_group(self, lane: int, op: int, n: int, key: int, reqs: List[Request], cap: int = 0,
+                   trim: bool = False) -> None:
+        if trim:
+            self.backend.trim(lane)
+            cap = max(cap, int(self.backend.held_bytes(lane)))  # the floor trimming keeps
+        self.backend.limit_lane(lane, cap)
         t0 = self.clock()
         for r in reqs:
             r.start = t0
@@ -338,6 +348,15 @@ class LibraryBackend(Backend):
         # decapsulation hash) that is two streams per lane, each given a hardware queue
         self._streams = [c.stream_handle for c in self._lanes]
         self.pids = {n: lwe.param_id(n) for n in ns}
+        # The library's exact footprint depends only on (set, op, count) and the tuning.  The
+        # scheduler asks for it under its lock for every candidate group, so the table is
+        # filled here: a foreign call there waits for the interpreter lock, which the other
+        # threads may hold for a whole switch interval, and it stalls every dispatch.
+        self._call_bytes: Dict[Tuple[int, int, int], int] = {}
+        for n in ns:
+            for op in (KEYGEN, ENCAPS, DECAPS):
+                for count in range(1, CALL_BYTES_TABLE + 1):
+                    self._call_bytes[(n, op, count)] = self._lanes[0].call_bytes(self.pids[n], op, count)
         self.params = {n: lwe.params(self.pids[n]) for n in ns}
         self.keys: Dict[int, List[Tuple]] = {}
         g = lwe_inputs.rng(key_seed, 0)
@@ -367,7 +386,11 @@ class LibraryBackend(Backend):
         self._lanes[lane].trim()
 
     def call_bytes(self, n: int, op: int, count: int) -> Optional[int]:
-        return self._lanes[0].call_bytes(self.pids[n], op, count)
+        k = (n, op, count)
+        b = self._call_bytes.get(k)
+        if b is None:
+            b = self._call_bytes[k] = self._lanes[0].call_bytes(self.pids[n], op, count)
+        return b
 
     def host_key(self, n: int, key: int):
         return self.keys[n][key][2], self.keys[n][key][3]
