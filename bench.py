@@ -379,6 +379,7 @@ def main():
         c.set_side_stream(args.lane_side_stream)
         c.set_hash_lanes(args.lane_hash_lanes)
     streams = [torch.cuda.ExternalStream(c.stream_handle, device=dev) for c in ctxs]
+    handles = [c.stream_handle for c in ctxs]
     ctx = ctxs[0]
     if args.unfused:
         for c in ctxs:
@@ -404,11 +405,11 @@ def main():
     torch.cuda.synchronize()
 
     def step(i, lane):
-        c, st, bf = ctxs[lane], streams[lane], bufs[lane]
-        with torch.cuda.stream(st):
-            c.keygen(pid, d_seedA[i], d_seedSK[i], d_z[i], bf["pk"], bf["sk"])
-            c.encaps_batch(pid, B, bf["pk"], d_mu, bf["ct"], bf["ss"])
-            c.decaps_batch(pid, B, bf["sk"], bf["ct"], bf["ss2"])
+        c, bf = ctxs[lane], bufs[lane]
+        h = handles[lane]
+        c.keygen(pid, d_seedA[i], d_seedSK[i], d_z[i], bf["pk"], bf["sk"], stream=h)
+        c.encaps_batch(pid, B, bf["pk"], d_mu, bf["ct"], bf["ss"], stream=h)
+        c.decaps_batch(pid, B, bf["sk"], bf["ct"], bf["ss2"], stream=h)
 
     for i in range(W):
         for lane in range(S):
@@ -434,11 +435,9 @@ def main():
             try:
                 go.wait()
                 for i in range(lane, K, lanes):
-                    with torch.cuda.stream(streams[lane]):
-                        ev[i][0].record()
+                    ev[i][0].record(streams[lane])
                     step(first_seed + i, lane)
-                    with torch.cuda.stream(streams[lane]):
-                        ev[i][1].record()
+                    ev[i][1].record(streams[lane])
             except Exception as e:  # surfaced after the join
                 errors.append(e)
 

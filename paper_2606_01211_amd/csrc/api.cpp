@@ -60,7 +60,9 @@ struct lwe_ctx {
   bool device_hash_only = false;  // never hash on the host (no host staging)
   uint32_t* d_T0 = nullptr;
   Buf bufs[B_COUNT];
-  // cache of the last public key hashed on the host
+  // cache of the last public key hashed on the host; host callbacks of queued calls read and
+  // fill it on the runtime's thread, so it is guarded
+  std::mutex pk_mu;
   std::vector<uint8_t> pk_cache;
   uint8_t pkh_cache[32];
   // Pinned host staging of the host hashing paths (public keys down, their hashes up), so that
@@ -548,6 +550,7 @@ int check_pid(int pid, const Params** pp) {
 }
 
 void host_pkh(lwe_ctx* c, const uint8_t* pk, size_t len, uint8_t out[32]) {
+  std::lock_guard<std::mutex> lk(c->pk_mu);
   if (c->pk_cache.size() == len && memcmp(c->pk_cache.data(), pk, len) == 0) {
     memcpy(out, c->pkh_cache, 32);
     return;
@@ -555,6 +558,47 @@ void host_pkh(lwe_ctx* c, const uint8_t* pk, size_t len, uint8_t out[32]) {
   sha3_256(pk, len, out);
   c->pk_cache.assign(pk, pk + len);
   memcpy(c->pkh_cache, out, 32);
+}
+
+// Host hashing in stream order: a host function queued on the stream hashes `count` records of
+// `len` bytes at `src` (pinned staging, filled by a copy queued before it) into `out` (pinned
+// staging, read by a copy queued after it).  The calling thread does not wait for the device:
+// under load a small copy can take milliseconds to be scheduled, and a caller blocked on it
+// cannot queue its next work meanwhile.  `lookup`: one public key, hashed through the cache;
+// `remember`: the last record becomes the cached key.  The function runs on the runtime's
+// thread and makes no runtime calls.
+struct HostHashJob {
+  lwe_ctx* c;
+  const uint8_t* src;
+  size_t len, count;
+  uint8_t* out;
+  bool lookup, remember;
+};
+
+void host_hash_cb(void* arg) {
+  HostHashJob* j = (HostHashJob*)arg;
+  if (j->lookup) {
+    host_pkh(j->c, j->src, j->len, j->out);
+  } else {
+    host_for(j->c->host_threads, j->count, [&](size_t i) { sha3_256(j->src + i * j->len, j->len, j->out + i * 32); });
+    if (j->remember) {
+      std::lock_guard<std::mutex> lk(j->c->pk_mu);
+      j->c->pk_cache.assign(j->src + (j->count - 1) * j->len, j->src + j->count * j->len);
+      memcpy(j->c->pkh_cache, j->out + (j->count - 1) * 32, 32);
+    }
+  }
+  delete j;
+}
+
+int host_hash_async(lwe_ctx* c, const uint8_t* src, size_t len, size_t count, uint8_t* out, bool lookup,
+                    bool remember, hipStream_t s) {
+  HostHashJob* j = new HostHashJob{c, src, len, count, out, lookup, remember};
+  if (hipLaunchHostFunc(s, host_hash_cb, j) != hipSuccess) {
+    (void)hipGetLastError();
+    delete j;
+    return LWE_EDEVICE;
+  }
+  return LWE_OK;
 }
 
 // ------------------------------------------------------------------------------------
@@ -1235,17 +1279,14 @@ int lwe_keygen_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* seedA, co
                              hipMemcpyDeviceToDevice, s));
   HIP_CHECK(hipMemcpy2DAsync(osk.dev + off_z, p.sk_bytes, dZ, 32, 32, count, hipMemcpyDeviceToDevice, s));
   if (use_host_hash(c, pid, count)) {
-    // public keys down and their hashes up through the pinned staging; no wait after the
-    // upload (the staging is next written after a later wait on this context's stream)
+    // public keys down, hashed on the host in stream order, hashes up, all through the pinned
+    // staging (every use of it is ordered on the context's calls); the newest key's hash is
+    // left in the cache for an encapsulation against it
     uint8_t* hpk;
     LWE_CHECK(host_pinned(c, count * (p.pk_bytes + 32), s, &hpk));
     uint8_t* hh = hpk + count * p.pk_bytes;
     HIP_CHECK(hipMemcpyAsync(hpk, opk.dev, count * p.pk_bytes, hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipStreamSynchronize(s));
-    host_for(c->host_threads, count, [&](size_t i) { sha3_256(hpk + i * p.pk_bytes, p.pk_bytes, hh + i * 32); });
-    // an encapsulation against the newest key finds its hash in the cache
-    c->pk_cache.assign(hpk + (count - 1) * p.pk_bytes, hpk + count * p.pk_bytes);
-    memcpy(c->pkh_cache, hh + (count - 1) * 32, 32);
+    LWE_CHECK(host_hash_async(c, hpk, p.pk_bytes, count, hh, false, true, s));
     uint8_t* dh;
     LWE_CHECK(ensure_t(c, B_HCT, count * 32, &dh));
     HIP_CHECK(hipMemcpyAsync(dh, hh, count * 32, hipMemcpyHostToDevice, s));
@@ -1294,13 +1335,12 @@ int lwe_encaps_batch(lwe_ctx* c, int pid, size_t count, const uint8_t* pk, const
     LWE_CHECK(host_copy2(pk, p.pk_bytes, hpk, mu, count * mb, hmu, s));
     host_pkh(c, hpk.data(), p.pk_bytes, pkh);
   } else if (is_device_ptr(pk)) {
-    // the key down and its hash up through the pinned staging
+    // the key down, hashed (or found in the cache) on the host in stream order, its hash up:
+    // through the pinned staging, without waiting here
     uint8_t* st;
     LWE_CHECK(host_pinned(c, p.pk_bytes + 32, s, &st));
     HIP_CHECK(hipMemcpyAsync(st, pk, p.pk_bytes, hipMemcpyDeviceToHost, s));
-    HIP_CHECK(hipStreamSynchronize(s));
-    host_pkh(c, st, p.pk_bytes, st + p.pk_bytes);
-    memcpy(pkh, st + p.pk_bytes, 32);
+    LWE_CHECK(host_hash_async(c, st, p.pk_bytes, 1, st + p.pk_bytes, true, false, s));
     pkh_src = st + p.pk_bytes;
   } else {
     host_pkh(c, pk, p.pk_bytes, pkh);

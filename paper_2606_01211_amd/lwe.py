@@ -193,12 +193,21 @@ def register_params(n: int, logq: int, B: int, K: int, sigma: float) -> int:
     return pid
 
 
+_PARAMS: dict = {}
+
+
 def params(pid: int) -> Params:
+    # the registry is fixed once the library is loaded, so each set is asked for once: every
+    # call below starts here, and a foreign call would give up the interpreter lock each time
+    pp = _PARAMS.get(pid)
+    if pp is not None:
+        return pp
     info = ParamInfo()
     _check(lib().lwe_param_get(pid, C.byref(info)), "lwe_param_get")
-    return Params(pid, info.n, info.logq, info.B, info.K, info.sigma, info.pk_bytes,
-                  info.sk_bytes, info.ct_bytes, info.mu_bytes, info.paper, info.q, info.nbar, info.mbar,
-                  info.coef_bytes, info.eta, info.k)
+    pp = _PARAMS[pid] = Params(pid, info.n, info.logq, info.B, info.K, info.sigma, info.pk_bytes,
+                               info.sk_bytes, info.ct_bytes, info.mu_bytes, info.paper, info.q, info.nbar,
+                               info.mbar, info.coef_bytes, info.eta, info.k)
+    return pp
 
 
 def cdf_table(pid: int) -> np.ndarray:
