@@ -15,7 +15,10 @@ is the largest divisor of --steps not above --streams (at least half of it), so 
 runs the same number of timed steps; the feeding threads start together after the device
 has drained.  `serial` is the same K steps on one lane with the same kernels, and the
 per-kernel times, `roofline` and `fused_product` come from it (stand-alone times of the
-kernels behind `value`); `kernels_pipelined` has the same kernels' times in the pipelined run.
+kernels behind `value`); `kernels_pipelined` has the same kernels' times in the pipelined run
+when the lanes are fed call by call (--eager).  By default each lane replays its step as a HIP
+graph captured from the same library calls (checked byte for byte against a call-by-call step
+first), so that the host work of the calls does not stagger the lanes.
 
 Also reported: the plain path (lwe_encaps / lwe_decaps one instance per call, wall and device
 time), the CPU oracle timed on this host over a bounded sample of the same workload (whose
@@ -99,6 +102,9 @@ def parse():
                          "(two streams per lane)")
     ap.add_argument("--lane-hash-lanes", type=int, default=2, choices=(1, 2),
                     help="lanes per record of the SHA3 kernels of every lane and of the serial run")
+    ap.add_argument("--eager", action="store_true",
+                    help="feed the pipelined lanes call by call instead of replaying each lane's step as "
+                         "a captured HIP graph")
     ap.add_argument("--hw-queues", type=int, default=0,
                     help="HIP hardware queues of this process (GPU_MAX_HW_QUEUES, at most 32; default "
                          "streams + 3, or 2 * streams + 2 with --lane-side-stream): every stream in "
@@ -391,8 +397,11 @@ def main():
     seedA, seedSK, z = lwe_inputs.keygen_seeds(g, W + 2 * K)
     mus = lwe_inputs.messages(g, B, p.mu_bytes)
     d_mu = torch.from_numpy(mus).to(dev)
-    # every input of the timed steps is resident in device memory before timing starts
-    d_seedA, d_seedSK, d_z = (torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in (seedA, seedSK, z))
+    # every input of the timed steps is resident in device memory before timing starts; a step's
+    # three seeds are one 64-byte row, loaded into its lane's seed slot by one copy
+    d_seeds = torch.from_numpy(np.ascontiguousarray(np.concatenate([seedA, seedSK, z], axis=1))).to(dev)
+    d_seedA, d_seedSK, d_z = d_seeds[:, 0:16], d_seeds[:, 16:32], d_seeds[:, 32:64]
+    slots = [torch.empty(64, dtype=torch.uint8, device=dev) for _ in range(S)]
     bufs = []
     for _ in range(S):
         bufs.append({
@@ -404,12 +413,23 @@ def main():
         })
     torch.cuda.synchronize()
 
-    def step(i, lane):
-        c, bf = ctxs[lane], bufs[lane]
-        h = handles[lane]
-        c.keygen(pid, d_seedA[i], d_seedSK[i], d_z[i], bf["pk"], bf["sk"], stream=h)
+    def lane_step(lane):
+        """One step on the lane's buffers, its seeds taken from the lane's seed slot."""
+        c, bf, h, sl = ctxs[lane], bufs[lane], handles[lane], slots[lane]
+        c.keygen(pid, sl[0:16], sl[16:32], sl[32:64], bf["pk"], bf["sk"], stream=h)
         c.encaps_batch(pid, B, bf["pk"], d_mu, bf["ct"], bf["ss"], stream=h)
         c.decaps_batch(pid, B, bf["sk"], bf["ct"], bf["ss2"], stream=h)
+
+    graphs = None
+
+    def step(i, lane):
+        """Step i (its seeds) on `lane`: the call sequence, or a replay of the lane's graph."""
+        with torch.cuda.stream(streams[lane]):
+            slots[lane].copy_(d_seeds[i])
+            if graphs is not None:
+                graphs[lane].replay()
+        if graphs is None:
+            lane_step(lane)
 
     for i in range(W):
         for lane in range(S):
@@ -419,14 +439,14 @@ def main():
 
     def timed(lanes, first_seed):
         """K steps spread round-robin over `lanes` streams, each stream fed by its own host
-        thread (a library call that hashes on the host waits for its own stream only; the
-        calls release the interpreter lock).  The feeding threads are started first and
-        released together by a barrier, after the device has drained, so the timed window
-        holds the K steps and nothing else.  Returns wall seconds, per-step device latencies
-        (ms) and the merged kernel profile."""
+        thread (the library calls queue their work without waiting for the device and release
+        the interpreter lock).  The feeding threads are started first and released together by
+        a barrier, after the device has drained, so the timed window holds the K steps and
+        nothing else.  Returns wall seconds, per-step device latencies (ms) and the merged
+        kernel profile (library calls only: a graph replay has no per-kernel events)."""
         for c in ctxs:
             c.prof_reset()
-            c.prof_enable(True)
+            c.prof_enable(graphs is None)
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
         errors = []
         go = threading.Barrier(lanes + 1)
@@ -467,12 +487,44 @@ def main():
         return t1 - t0, [e0.elapsed_time(e1) for e0, e1 in ev], prof
 
     # ---------------- batched, timed ----------------
-    # serial: the same K steps on one lane (stand-alone kernel times of the same kernels)
+    # serial: the same K steps on one lane, call by call, with every kernel bracketed by HIP
+    # events (stand-alone times of the kernels behind `value`)
     tx = Roctx()
     tx.push("leg:serial")
     wall1, step_ms1, prof1 = timed(1, W)
     tx.pop()
     serial_value = K * B / wall1
+    # The pipelined lanes replay their step as a HIP graph captured from the same library calls:
+    # the calls' own host work (about 35 runtime calls per step) serialises across feeding
+    # threads and staggers the lanes' start by about 0.25 ms per lane.  A replay runs the same
+    # kernels, copies and host hashing functions; it is checked against a call-by-call step of
+    # the same seeds before timing.
+    graph_check = None
+    if not args.eager and S > 1:
+        for c in ctxs:
+            c.prof_enable(False)
+        torch.cuda.synchronize()
+        caps = []
+        for lane in range(S):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.stream(streams[lane]):
+                slots[lane].copy_(d_seeds[0])
+                g.capture_begin(capture_error_mode="relaxed")
+                lane_step(lane)
+                g.capture_end()
+            caps.append(g)
+        torch.cuda.synchronize()
+        i_chk = W + 2 * K - 1
+        step(i_chk, 0)  # call by call (graphs not yet in use)
+        torch.cuda.synchronize()
+        want = [bufs[0][k].clone() for k in ("pk", "sk", "ct", "ss", "ss2")]
+        graphs = caps
+        step(i_chk, 0)
+        torch.cuda.synchronize()
+        graph_check = all(bool(torch.equal(a, bufs[0][k])) for a, k in zip(want, ("pk", "sk", "ct", "ss", "ss2")))
+        if not graph_check:
+            print("graph replay differs from the call sequence: timing call by call", file=sys.stderr, flush=True)
+            graphs = None
     if S > 1:
         tx.push("leg:pipelined")
         wall, step_ms, prof = timed(S, W + K)
@@ -644,7 +696,9 @@ def main():
         "hw_queues": int(os.environ["GPU_MAX_HW_QUEUES"]),
         "lane_side_stream": bool(args.lane_side_stream),
         "lane_hash_lanes": int(args.lane_hash_lanes),
-        "serial": {"value": serial_value, "ms_per_step": 1e3 * wall1 / K,
+        "lane_feed": "graph replay" if graphs is not None else "library calls",
+        "graph_matches_calls": graph_check,
+        "serial": {"value": serial_value, "ms_per_step": 1e3 * wall1 / K, "feed": "library calls",
                    "batch_latency_ms": {"p50": pct(step_ms1, 50), "p99": pct(step_ms1, 99)}},
         "plain": {"value": plain_rate, "unit": "encaps+decaps/s",
                   "encaps_ms": {"p50": pct(enc_ms, 50), "p99": pct(enc_ms, 99)},
@@ -654,13 +708,13 @@ def main():
                   "calls": len(enc_ms)},
         "batched_over_plain": value / plain_rate,
         "kernels": kern,
-        "kernels_pipelined": kern_table(prof),
+        "kernels_pipelined": kern_table(prof) if graphs is None else None,
         "roofline": roof,
         "fused_product": fused_product,
         "rooflines": rooflines,
         "cpu_baseline": None,
     }
-    bit_exact = device_agree and plain_ok
+    bit_exact = device_agree and plain_ok and graph_check is not False
 
     # ---------------- CPU oracle on a bounded sample ----------------
     if not args.no_cpu:

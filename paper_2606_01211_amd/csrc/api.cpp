@@ -6,6 +6,8 @@
 
 #include <algorithm>
 #include <map>
+#include <set>
+#include <tuple>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -34,6 +36,19 @@ struct Buf {
 };
 
 }  // namespace
+
+struct lwe_ctx;
+// Arguments of one host hashing function (host_hash_async).
+struct HostHashJob {
+  lwe_ctx* c;
+  const uint8_t* src;
+  size_t len, count;
+  uint8_t* out;
+  bool lookup, remember;
+  bool operator<(const HostHashJob& o) const {
+    return std::tie(src, len, count, out, lookup, remember) < std::tie(o.src, o.len, o.count, o.out, o.lookup, o.remember);
+  }
+};
 
 struct lwe_ctx {
   int device = 0;
@@ -70,6 +85,8 @@ struct lwe_ctx {
   // copies, which serialise the host threads of concurrent contexts.  Grown on demand.
   uint8_t* hpin = nullptr;
   size_t hpin_cap = 0;
+  // arguments of the queued host hashing functions (see host_hash_async)
+  std::set<HostHashJob> hash_jobs;
   lwe_tuning tuning[256];
   int host_threads = 1;
   // kernel timing (lwe_prof_*): events bracketing each launch, resolved lazily
@@ -566,17 +583,11 @@ void host_pkh(lwe_ctx* c, const uint8_t* pk, size_t len, uint8_t out[32]) {
 // under load a small copy can take milliseconds to be scheduled, and a caller blocked on it
 // cannot queue its next work meanwhile.  `lookup`: one public key, hashed through the cache;
 // `remember`: the last record becomes the cached key.  The function runs on the runtime's
-// thread and makes no runtime calls.
-struct HostHashJob {
-  lwe_ctx* c;
-  const uint8_t* src;
-  size_t len, count;
-  uint8_t* out;
-  bool lookup, remember;
-};
-
+// thread and makes no runtime calls.  Its arguments are a job owned by the context, one per
+// distinct set of arguments, never changed and kept until the context is destroyed: a call
+// captured into a graph runs the same job at every replay.
 void host_hash_cb(void* arg) {
-  HostHashJob* j = (HostHashJob*)arg;
+  const HostHashJob* j = (const HostHashJob*)arg;
   if (j->lookup) {
     host_pkh(j->c, j->src, j->len, j->out);
   } else {
@@ -587,17 +598,13 @@ void host_hash_cb(void* arg) {
       memcpy(j->c->pkh_cache, j->out + (j->count - 1) * 32, 32);
     }
   }
-  delete j;
 }
 
 int host_hash_async(lwe_ctx* c, const uint8_t* src, size_t len, size_t count, uint8_t* out, bool lookup,
                     bool remember, hipStream_t s) {
-  HostHashJob* j = new HostHashJob{c, src, len, count, out, lookup, remember};
-  if (hipLaunchHostFunc(s, host_hash_cb, j) != hipSuccess) {
-    (void)hipGetLastError();
-    delete j;
-    return LWE_EDEVICE;
-  }
+  const HostHashJob key{c, src, len, count, out, lookup, remember};
+  const HostHashJob* j = &*c->hash_jobs.insert(key).first;
+  HIP_CHECK(hipLaunchHostFunc(s, host_hash_cb, (void*)j));
   return LWE_OK;
 }
 
