@@ -781,9 +781,17 @@ def main():
             stop_at = time.perf_counter() + args.energy_seconds
 
             def spin(lane):
+                # at most two steps queued per lane, so the run ends near its time limit (graph
+                # replays return at once, and the host would otherwise queue seconds of work)
                 i = 0
+                marks = []
                 while time.perf_counter() < stop_at:
                     step(W + (i % (2 * K)), lane)
+                    ev = torch.cuda.Event()
+                    ev.record(streams[lane])
+                    marks.append(ev)
+                    if len(marks) > 2:
+                        marks.pop(0).synchronize()
                     i += 1
                 done[lane] = i
 
