@@ -1611,8 +1611,9 @@ __device__ __forceinline__ uint32_t interleave_in(uint32_t w, uint32_t sel) {
 // SHA3-256 of count records of len bytes, one record per pair of lanes.  Full 136-byte
 // blocks are read as 4-byte words (when aligned) and the next block is fetched while the
 // current one is permuted; the final block and the padding are assembled byte by byte.
-// At most 128 VGPRs (four waves per SIMD): a hash wave is a long dependent chain that shares
-// its CU with the product and sampler workgroups of other streams, and must leave them room.
+// Up to 256 VGPRs (two waves per SIMD): the build gives it 217 and no scratch.  A tighter
+// limit (128, four waves per SIMD, to leave room beside other streams' product and sampler
+// workgroups) spilled the state to scratch, 20 times the digests' bytes in writes per launch.
 // ALIGNED: every record starts at a 4-byte boundary (whole-word loads).
 template <bool ALIGNED>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
