@@ -53,6 +53,12 @@ PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # Algorithmic work per unit (see the design notes for the derivations)
 AES_OPS_PER_BLOCK = 160 + 160 + 40  # 160 table lookups, 160 XORs into the state, 40 round-key XORs (10 rounds)
 KECCAK_OPS_PER_PERM = 24 * (50 + 50 + 50 + 50 + 2)  # theta, rho, pi-chi (ANDN+XOR), iota per round on 32-bit halves
+# Per AES block of the sampler's compiled kernel (k_sample<6>): VALU instructions (cipher, CDF
+# compare and store, from SQ_INSTS_VALU over the blocks of a launch) and LDS table lookups
+SAMPLE_VALU_PER_BLOCK = 409
+SAMPLE_LDS_PER_BLOCK = 148
+# LDS: 256 CUs x 128 bytes per clock x 2.4 GHz
+PEAK_LDS_TBS = 256 * 128 * 2.4e9 / 1e12
 
 
 class Roctx:
@@ -625,6 +631,16 @@ def main():
         blocks = 2 * n + 2 * B * (2 * n + 8)
         rooflines["sample"]["keystream_GBps"] = blocks * 16 / (kern["sample"]["total_ms"] * 1e-3 / K) / 1e9
         rooflines["sample"]["aes_Gblocks_s"] = blocks / (kern["sample"]["total_ms"] * 1e-3 / K) / 1e9
+        # The sampler against the issue bound of its own instruction stream: blocks x VALU
+        # instructions per block over the chip's 32-bit VALU rate, and blocks x LDS lookups per
+        # block x 4 bytes over the chip's LDS bandwidth (per-block counts of the compiled kernel).
+        t_s = kern["sample"]["total_ms"] * 1e-3 / K
+        valu_s = blocks * SAMPLE_VALU_PER_BLOCK / (PEAK_VALU_TOPS * 1e12)
+        lds_s = blocks * SAMPLE_LDS_PER_BLOCK * 4 / (PEAK_LDS_TBS * 1e12)
+        rooflines["sample"]["issue_bound"] = {
+            "valu_instr_per_block": SAMPLE_VALU_PER_BLOCK, "lds_lookups_per_block": SAMPLE_LDS_PER_BLOCK,
+            "valu_bound_us_per_step": 1e6 * valu_s, "lds_bound_us_per_step": 1e6 * lds_s,
+            "measured_us_per_step": 1e6 * t_s, "frac": max(valu_s, lds_s) / t_s}
     if "prod_strip" in rooflines:
         mch = ctx.get_tuning(pid)["m_chunks"] or 8
         fused = not args.unfused

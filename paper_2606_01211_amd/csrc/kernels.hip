@@ -564,7 +564,27 @@ __global__ void __launch_bounds__(64 * SAMPLE_WAVES) k_sample(SampleArgs a, int 
   const uint32_t off0 = (uint32_t)(lane & 31) << 2, off2 = off0 + 128;
   const int n = a.n;
   const uint32_t nb = (uint32_t)n >> 3, magic = 0xffffffffu / (2u * nb) + 1u;
-  const int total = 2 * n + (a.nseg == 3 ? 8 : 0);  // AES blocks per instance
+  // Segment 0 in fragment order is walked slot by slot, so that 16 consecutive lanes fill one
+  // whole 128-byte line of the fragment (an instance's 8 rows x 16 columns of one step) and a
+  // store never leaves a line partly written: slot ((s * 4 + c) * 8 + r) * 2 + h is the block of
+  // row r, columns 64 s + 16 c + 8 h .. +7.  Slots past column n (the last step of an n that is
+  // not a multiple of 64) have no block.  Row-major segments are walked block by block.
+  const int p0 = a.x_frag ? 64 * ((n + 63) >> 6) : n;  // segment 0's slots
+  const int total = p0 + n + (a.nseg == 3 ? 8 : 0);   // slots per instance
+  // block index within its segment of slot t, and whether the slot has a block
+  auto block_of = [&](int t, int seg, bool& has) __attribute__((always_inline)) -> uint32_t {
+    has = true;
+    if (seg == 1) return (uint32_t)(t - p0);
+    if (seg == 2) return (uint32_t)(t - p0 - n);
+    if (!a.x_frag) return (uint32_t)t;
+    const uint32_t col = 64u * (uint32_t)(t >> 6) + 16u * ((uint32_t)(t >> 4) & 3u) + 8u * ((uint32_t)t & 1u);
+    has = col < (uint32_t)n;
+    return ((uint32_t)(t >> 1) & 7u) * nb + (col >> 3);
+  };
+  auto seg_of = [&](int t) __attribute__((always_inline)) { return t < p0 ? 0 : (t < p0 + n ? 1 : 2); };
+  // this lane's block and first column within a 64-slot step of segment 0's fragment order
+  const uint32_t lane_blk = (((uint32_t)lane >> 1) & 7u) * nb + (((uint32_t)lane >> 4) & 3u) * 2u + ((uint32_t)lane & 1u);
+  const uint32_t lane_col = (((uint32_t)lane >> 4) & 3u) * 16u + ((uint32_t)lane & 1u) * 8u;
   // Work unit = 64 * SAMPLE_ILP consecutive blocks of one instance, taken by one wave, so
   // that the instance's round keys are wave-uniform (scalar registers).
   const int per_unit = 64 * SAMPLE_ILP;
@@ -587,38 +607,44 @@ __global__ void __launch_bounds__(64 * SAMPLE_WAVES) k_sample(SampleArgs a, int 
     }
     uint32_t o[SAMPLE_ILP][4];
     const int t_first = chunk * per_unit, t_last = min(t_first + per_unit - 1, total - 1);
-    const int seg_first = t_first < n ? 0 : (t_first < 2 * n ? 1 : 2);
-    const int seg_last = t_last < n ? 0 : (t_last < 2 * n ? 1 : 2);
+    const int seg_first = seg_of(t_first), seg_last = seg_of(t_last);
     if (seg_first == seg_last) {
       // A unit inside one segment (the usual case) has a wave-uniform domain word: round 1's
-      // fixed lookups are done once for its blocks, and the segment's stores are uniform.
+      // fixed lookups are done once for its blocks, and the segment's stores are uniform.  In
+      // segment 0's fragment order a unit starts on a 64-slot step, so slot t_first + 64 j + lane
+      // is lane_blk + 8 (step) with a wave-uniform step (all of the unit's slots exist there).
+      const bool fragw = seg_first == 0 && a.x_frag;
+      const int seg_base = seg_first == 0 ? 0 : (seg_first == 1 ? p0 : p0 + n);
       uint32_t fx[6];
       aes_round1_fixed_rep(TR, off0, off2, rk, rkr, bswap32((uint32_t)(seg_first + 1)), fx);
 #pragma unroll
       for (int j = 0; j < SAMPLE_ILP; ++j) {
         const int t = t_first + j * 64 + lane;
-        const int tc = t < total ? t : total - 1;
-        aes_ctr_block_rep_fixed(TR, off0, off2, rk, rkr, fx, (uint32_t)(tc - seg_first * n), o[j]);
+        const uint32_t lb = fragw ? lane_blk + 8u * (uint32_t)((t_first >> 6) + j)
+                                  : (uint32_t)((t <= t_last ? t : t_last) - seg_base);
+        aes_ctr_block_rep_fixed(TR, off0, off2, rk, rkr, fx, lb, o[j]);
       }
 #pragma unroll
       for (int j = 0; j < SAMPLE_ILP; ++j) {
         const int t = t_first + j * 64 + lane;
-        if (t <= t_last) sample_store<KT>(a, inst, seg_first, (uint32_t)(t - seg_first * n), nb, magic, o[j]);
+        if (fragw) {
+          if (lane_col + 64u * (uint32_t)((t_first >> 6) + j) < (uint32_t)n)
+            sample_store<KT>(a, inst, 0, lane_blk + 8u * (uint32_t)((t_first >> 6) + j), nb, magic, o[j]);
+        } else if (t <= t_last) {
+          sample_store<KT>(a, inst, seg_first, (uint32_t)(t - seg_base), nb, magic, o[j]);
+        }
       }
     } else {
-      int seg[SAMPLE_ILP];
-#pragma unroll
+      // a unit across segments (at most two per instance): one block at a time
+#pragma unroll 1
       for (int j = 0; j < SAMPLE_ILP; ++j) {
         const int t = t_first + j * 64 + lane;
         const int tc = t < total ? t : total - 1;
-        seg[j] = tc < n ? 0 : (tc < 2 * n ? 1 : 2);
-        aes_ctr_block_rep(TR, off0, off2, rk, rkr, bswap32((uint32_t)(seg[j] + 1)),
-                          (uint64_t)(tc - seg[j] * n), o[j]);
-      }
-#pragma unroll
-      for (int j = 0; j < SAMPLE_ILP; ++j) {
-        const int t = t_first + j * 64 + lane;
-        if (t < total) sample_store<KT>(a, inst, seg[j], (uint32_t)(t - seg[j] * n), nb, magic, o[j]);
+        const int seg = seg_of(tc);
+        bool has;
+        const uint32_t lb = block_of(tc, seg, has);
+        aes_ctr_block_rep(TR, off0, off2, rk, rkr, bswap32((uint32_t)(seg + 1)), (uint64_t)lb, o[0]);
+        if (has && t < total) sample_store<KT>(a, inst, seg, lb, nb, magic, o[0]);
       }
     }
   }
@@ -1875,7 +1901,8 @@ hipError_t launch_sample_stream(const Params& p, const uint32_t* rk, const uint3
 hipError_t launch_sample(const SampleArgs& a, int count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   // persistent waves: at most two workgroups (64 KB of tables each) per CU
-  const int total = 2 * a.n + (a.nseg == 3 ? 8 : 0);
+  const int p0 = a.x_frag ? 64 * ((a.n + 63) >> 6) : a.n;  // segment 0's slots, as in k_sample
+  const int total = p0 + a.n + (a.nseg == 3 ? 8 : 0);
   const long long units = (long long)((total + 64 * SAMPLE_ILP - 1) / (64 * SAMPLE_ILP)) * count;
   const unsigned grid = (unsigned)std::min<long long>((units + SAMPLE_WAVES - 1) / SAMPLE_WAVES, 2 * g_num_cus);
   switch (a.K) {
