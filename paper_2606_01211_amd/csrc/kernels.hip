@@ -987,7 +987,9 @@ constexpr int STRIP_WAVES = 8;
 // fragments are requested UNR - 1 steps ahead; the strip is padded to a multiple of UNR).
 // TAB: where the strip comes from.  0: the expanded copy a.Amat (unfused variant; the loop
 // and epilogue are the same); 1: AES with the 4 KB tables; 2: AES with the 32 KB
-// conflict-free tables (when they fit beside the strip).
+// conflict-free tables; 3: AES with the sampler's 64 KB conflict-free tables (one address
+// per byte move, one rotation per column; about half of TAB 2's instructions per block).
+// The launch takes the largest tables that fit beside the strip.
 template <int CG, int RG, bool CMP, int UNR, int TAB>
 __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
   constexpr bool MAT = TAB == 0;
@@ -995,7 +997,7 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
   constexpr int YD = (UNR * CG) % 3 == 0 ? 3 : 2;
   static_assert((UNR * CG) % YD == 0, "strip fragment ring does not tile the loop body");
   // static: a compile-time address for the table lookups
-  __shared__ uint32_t T[TAB == 2 ? TQ_WORDS : (TAB == 1 ? 1024 : 1)];
+  __shared__ uint32_t T[TAB == 3 ? TR_WORDS : (TAB == 2 ? TQ_WORDS : (TAB == 1 ? 1024 : 1))];
   extern __shared__ uint32_t smem[];
   uint8_t* strip = (uint8_t*)smem;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1024,10 +1026,12 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
 
   if constexpr (TAB == 1) load_tables(T, a.T0);
   if constexpr (TAB == 2) load_tables_q(T, a.T0);
+  if constexpr (TAB == 3) load_tables_rep(T, a.T0);
   __syncthreads();
   // domain 0 and block indices below 2^32 (n <= 32768): round 1's fixed part once per workgroup
   uint32_t fx[6];
   if constexpr (TAB == 2) aes_round1_fixed_q(T, qoff, rk, rkr, 0u, fx);
+  if constexpr (TAB == 3) aes_round1_fixed_rep(T, qoff, qoff + 128, rk, rkr, 0u, fx);
 
   // ---- regenerate (or, unfused, copy) the strip ----
   // Item t = one AES block = 8 consecutive contraction rows of one column.  Items are
@@ -1082,8 +1086,10 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
         w[j][0] = v.x; w[j][1] = v.y; w[j][2] = v.z; w[j][3] = v.w;
       } else if constexpr (TAB == 1) {
         aes_ctr_block(T, rk, 0u, ((uint64_t)c * n + k) >> 3, w[j]);
-      } else {
+      } else if constexpr (TAB == 2) {
         aes_ctr_block_q_fixed(T, qoff, rk, rkr, fx, (uint32_t)(((uint64_t)c * n + k) >> 3), w[j]);
+      } else {
+        aes_ctr_block_rep_fixed(T, qoff, qoff + 128, rk, rkr, fx, (uint32_t)(((uint64_t)c * n + k) >> 3), w[j]);
       }
     }
 #pragma unroll
@@ -1960,13 +1966,17 @@ int product_strip_unroll(int, int, int) { return 3; }
 template <int CG, int RG, int UNR>
 static hipError_t launch_strip_t(const ProdArgs& a, hipStream_t s) {
   const size_t lds = product_strip_lds_bytes(CG, a.kc_len, UNR) - 4096;  // the T-tables are static
-  // the conflict-free tables when they fit beside the strip, else the 4 KB ones
-  const int tab = a.Amat ? 0 : (lds + TQ_WORDS * 4 <= 160 * 1024 ? 2 : 1);
+  // the largest conflict-free tables that fit beside the strip, else the 4 KB ones
+  const int tab = a.Amat ? 0
+                : lds + TR_WORDS * 4 <= 160 * 1024 ? 3
+                : lds + TQ_WORDS * 4 <= 160 * 1024 ? 2
+                                                   : 1;
   // compare mode reads the received ciphertexts instead of writing them
   const bool cmp = a.mode == PM_COMPARE;
   auto kern = tab == 0 ? (cmp ? k_prod_strip<CG, RG, true, UNR, 0> : k_prod_strip<CG, RG, false, UNR, 0>)
             : tab == 1 ? (cmp ? k_prod_strip<CG, RG, true, UNR, 1> : k_prod_strip<CG, RG, false, UNR, 1>)
-                       : (cmp ? k_prod_strip<CG, RG, true, UNR, 2> : k_prod_strip<CG, RG, false, UNR, 2>);
+            : tab == 2 ? (cmp ? k_prod_strip<CG, RG, true, UNR, 2> : k_prod_strip<CG, RG, false, UNR, 2>)
+                       : (cmp ? k_prod_strip<CG, RG, true, UNR, 3> : k_prod_strip<CG, RG, false, UNR, 3>);
   const int total = a.n_jt * a.n_kc * a.n_mt;
   const unsigned grid = (unsigned)(8 * ((total + 7) / 8));
   hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * STRIP_WAVES), lds, s, a);
@@ -2057,14 +2067,16 @@ hipError_t launch_final_ss(int count, const uint32_t* flags, const uint8_t* kpri
 
 template <int CG, int RG, int UNR>
 static hipError_t allow_lds_strip_u() {
-  const void* kerns[6] = {(const void*)k_prod_strip<CG, RG, false, UNR, 0>,
+  const void* kerns[8] = {(const void*)k_prod_strip<CG, RG, false, UNR, 0>,
                           (const void*)k_prod_strip<CG, RG, true, UNR, 0>,
                           (const void*)k_prod_strip<CG, RG, false, UNR, 1>,
                           (const void*)k_prod_strip<CG, RG, true, UNR, 1>,
                           (const void*)k_prod_strip<CG, RG, false, UNR, 2>,
-                          (const void*)k_prod_strip<CG, RG, true, UNR, 2>};
-  for (int i = 0; i < 6; ++i) {
-    const int dyn = 160 * 1024 - (i >= 4 ? TQ_WORDS * 4 : 4096);
+                          (const void*)k_prod_strip<CG, RG, true, UNR, 2>,
+                          (const void*)k_prod_strip<CG, RG, false, UNR, 3>,
+                          (const void*)k_prod_strip<CG, RG, true, UNR, 3>};
+  for (int i = 0; i < 8; ++i) {
+    const int dyn = 160 * 1024 - (i >= 6 ? TR_WORDS * 4 : (i >= 4 ? TQ_WORDS * 4 : 4096));
     hipError_t e = hipFuncSetAttribute(kerns[i], hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     if (e != hipSuccess) return e;
   }

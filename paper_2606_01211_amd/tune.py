@@ -28,7 +28,7 @@ TABLE = os.path.join(HERE, "tuning.json")
 
 # (col_groups, row_groups) pairs the library instantiates
 SHAPES = [(1, 2), (1, 4), (2, 2), (2, 4), (3, 2), (3, 4)]
-M_CHUNKS = [4, 6, 8, 12, 16, 24]
+M_CHUNKS = [4, 5, 6, 7, 8, 12, 16, 24]
 
 
 def lds_fits(cg: int, n: int) -> bool:
