@@ -57,6 +57,10 @@ KECCAK_OPS_PER_PERM = 24 * (50 + 50 + 50 + 50 + 2)  # theta, rho, pi-chi (ANDN+X
 # compare and store, from SQ_INSTS_VALU over the blocks of a launch) and LDS table lookups
 SAMPLE_VALU_PER_BLOCK = 409
 SAMPLE_LDS_PER_BLOCK = 148
+# Per absorbed block, per wave of the two-lane SHA3 kernel (k_hash_records): two passes of the
+# 12-round permutation body (1317 instructions each) plus the block's load and bit
+# interleaving; SQ_INSTS_VALU gives 475 K per wave for 160 blocks
+HASH_VALU_PER_BLOCK = 2960
 # LDS: 256 CUs x 128 bytes per clock x 2.4 GHz
 PEAK_LDS_TBS = 256 * 128 * 2.4e9 / 1e12
 
@@ -641,6 +645,16 @@ def main():
             "valu_instr_per_block": SAMPLE_VALU_PER_BLOCK, "lds_lookups_per_block": SAMPLE_LDS_PER_BLOCK,
             "valu_bound_us_per_step": 1e6 * valu_s, "lds_bound_us_per_step": 1e6 * lds_s,
             "measured_us_per_step": 1e6 * t_s, "frac": max(valu_s, lds_s) / t_s}
+    if "hash_records" in rooflines and args.lane_hash_lanes == 2:
+        # Each record pair of lanes is one dependent chain of ct_perms absorbed blocks; a wave
+        # issues at most one VALU instruction per 4 cycles.  The chain's issue bound per launch
+        # is ct_perms x instructions per block x 4 cycles at the 2.4 GHz clock.
+        t_h = kern["hash_records"]["avg_us"] * 1e-6
+        chain_s = ct_perms * HASH_VALU_PER_BLOCK * 4 / 2.4e9
+        rooflines["hash_records"]["issue_bound"] = {
+            "valu_instr_per_block_per_wave": HASH_VALU_PER_BLOCK, "blocks_per_record": ct_perms,
+            "waves_per_launch": 2 * B // 64, "chain_bound_us": 1e6 * chain_s, "measured_us": 1e6 * t_h,
+            "frac": chain_s / t_h}
     if "prod_strip" in rooflines:
         mch = ctx.get_tuning(pid)["m_chunks"] or 8
         fused = not args.unfused
