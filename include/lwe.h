@@ -32,8 +32,13 @@
  *     reference after the call returns.
  *   - hip_stream == NULL runs the call synchronously on the context's own stream.  Otherwise
  *     device work is queued on that stream (a hipStream_t).  Calls whose outputs include
- *     host memory, and calls that hash on the host, synchronise the stream before returning;
- *     device outputs are valid once the stream has been synchronised.
+ *     host memory synchronise the stream before returning, and so do Encaps and Decaps of
+ *     batches up to the host-hashing size (16 unless tuned: lwe_tuning.host_hash_max), which
+ *     hash on the host between device phases.  Every other call on device buffers returns
+ *     once its work is queued: KeyGen's public-key hashes and Encaps' H(pk) are computed on
+ *     the host by functions queued on the stream (hipLaunchHostFunc), in stream order, so
+ *     such calls can also be captured into a HIP graph and replayed.  Device outputs are
+ *     valid once the stream has been synchronised.
  *   - The return value is an lwe_status.  On error, outputs are unspecified.
  *   - A context is not thread-safe: use one context per host thread.  Calls on one context
  *     execute on the device in the order they are made, whatever streams they are given: a
