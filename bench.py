@@ -54,8 +54,9 @@ PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 AES_OPS_PER_BLOCK = 160 + 160 + 40  # 160 table lookups, 160 XORs into the state, 40 round-key XORs (10 rounds)
 KECCAK_OPS_PER_PERM = 24 * (50 + 50 + 50 + 50 + 2)  # theta, rho, pi-chi (ANDN+XOR), iota per round on 32-bit halves
 # Per AES block of the sampler's compiled kernel (k_sample<6>): VALU instructions (cipher, CDF
-# compare and store, from SQ_INSTS_VALU over the blocks of a launch) and LDS table lookups
-SAMPLE_VALU_PER_BLOCK = 409
+# compare and store: SQ_INSTS_VALU over the blocks of a launch, 69.9 M x 64 / 11.04 M) and LDS
+# table lookups (the cipher's 148 per block with round 1's fixed part hoisted)
+SAMPLE_VALU_PER_BLOCK = 405
 SAMPLE_LDS_PER_BLOCK = 148
 # Per absorbed block, per wave of the two-lane SHA3 kernel (k_hash_records): two passes of the
 # 12-round permutation body (1317 instructions each) plus the block's load and bit
