@@ -37,8 +37,11 @@
  *     hash on the host between device phases.  Every other call on device buffers returns
  *     once its work is queued: KeyGen's public-key hashes and Encaps' H(pk) are computed on
  *     the host by functions queued on the stream (hipLaunchHostFunc), in stream order, so
- *     such calls can also be captured into a HIP graph and replayed.  Device outputs are
- *     valid once the stream has been synchronised.
+ *     such calls can also be captured into a HIP graph and replayed.  A captured graph uses
+ *     the context's working buffers as they were at capture: replay it only while no call
+ *     on that context needs larger ones (a larger batch or set grows, and so moves, them),
+ *     and not after lwe_ctx_trim.  Device outputs are valid once the stream has been
+ *     synchronised.
  *   - The return value is an lwe_status.  On error, outputs are unspecified.
  *   - A context is not thread-safe: use one context per host thread.  Calls on one context
  *     execute on the device in the order they are made, whatever streams they are given: a
