@@ -1000,7 +1000,7 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
   __shared__ uint32_t T[TAB == 3 ? TR_WORDS : (TAB == 2 ? TQ_WORDS : (TAB == 1 ? 1024 : 1))];
   extern __shared__ uint32_t smem[];
   uint8_t* strip = (uint8_t*)smem;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int total = a.n_jt * a.n_kc * a.n_mt;
   const int per = (total + 7) / 8;
   const int v = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
@@ -1121,24 +1121,25 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
   // workgroups (the strip holding V's columns, split-K) take the general epilogue.
   const bool fast = a.n_kc == 1 && nn0 + 16 * CG <= n;
   const int xsteps = a.ldx >> 6;
-  auto row_ptrs = [&](int rb, const int8_t* (&p)[RG]) __attribute__((always_inline)) {
+  auto row_offs = [&](int rb, size_t (&o)[RG]) __attribute__((always_inline)) {
     const int rbase = m_begin + rb * 16 * RG;
 #pragma unroll
     for (int rg = 0; rg < RG; ++rg) {
       const int g0 = rbase + rg * 16;  // groups past the chunk end read the chunk's first one
-      p[rg] = a.X + ((size_t)((g0 < m_end ? g0 : m_begin) >> 4) * xsteps + (k0 >> 6)) * 1024 + 16 * lane;
+      o[rg] = ((size_t)((g0 < m_end ? g0 : m_begin) >> 4) * xsteps + (k0 >> 6)) * 1024;
     }
   };
-  const int8_t* xp[RG];  // current row block
-  const int8_t* xq[RG];  // next row block of this wave (the current one if there is none)
-  row_ptrs(wave, xp);
-  row_ptrs(wave + STRIP_WAVES < nrb ? wave + STRIP_WAVES : wave, xq);
+  size_t xp[RG];  // current row block
+  size_t xq[RG];  // next row block of this wave (the current one if there is none)
+  row_offs(wave, xp);
+  row_offs(wave + STRIP_WAVES < nrb ? wave + STRIP_WAVES : wave, xq);
+  const int lane16 = 16 * lane;
 
   v4i xb[UNR][RG];  // X ring: slot = step mod UNR
   v4i yb[YD][2];    // strip fragment ring: slot = phase mod YD, a phase being one (step, cg)
-  auto load_xs = [&](v4i (&dst)[RG], const int8_t* const (&p)[RG], int s) __attribute__((always_inline)) {
+  auto load_xs = [&](v4i (&dst)[RG], const size_t (&o)[RG], int s) __attribute__((always_inline)) {
 #pragma unroll
-    for (int rg = 0; rg < RG; ++rg) dst[rg] = *(const v4i*)(p[rg] + 1024 * (size_t)s);
+    for (int rg = 0; rg < RG; ++rg) dst[rg] = *(const v4i*)(a.X + (o[rg] + 1024 * (size_t)s) + lane16);
   };
   auto load_y = [&](v4i (&dst)[2], int s, int cg) __attribute__((always_inline)) {
     dst[0] = *(const v4i*)(strip + ((size_t)((s * CG + cg) * 2) * 64 + lane) * 16);
@@ -1153,21 +1154,22 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
   // next phase (wrapping from the last step to step 0, the strip being the same for every
   // row block).  Scheduling barriers keep every request ahead of the MFMAs that hide it; the
   // scheduler would otherwise sink the loads next to their first use.
-  auto body = [&](int s) __attribute__((always_inline)) {
+  auto body = [&](int s, auto last_tag) __attribute__((always_inline)) {
+    constexpr bool LAST = decltype(last_tag)::value;
 #pragma unroll
     for (int i = 0; i < UNR; ++i) {
       const int t = s + i, t2 = t + UNR - 1;
-      if (t2 < kst)
+      if (!LAST || i == 0)
         load_xs(xb[(i + UNR - 1) % UNR], xp, min(t2, klast));
       else
-        load_xs(xb[(i + UNR - 1) % UNR], xq, min(t2 - kst, klast));
+        load_xs(xb[(i + UNR - 1) % UNR], xq, min(i - 1, klast));
 #pragma unroll
       for (int cg = 0; cg < CG; ++cg) {
         const int ph = i * CG + cg;
         if (cg + 1 < CG)
           load_y(yb[(ph + 1) % YD], t, cg + 1);
         else
-          load_y(yb[(ph + 1) % YD], t + 1 < kst ? t + 1 : 0, 0);
+          load_y(yb[(ph + 1) % YD], (!LAST || i + 1 < UNR) ? t + 1 : 0, 0);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int rg = 0; rg < RG; ++rg) {
@@ -1191,7 +1193,9 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
       // Fast epilogue operands (E' words, and in compare mode the received ciphertext
       // words), loaded now so that their latency hides behind the contraction.  The loads
       // are unconditional (rows past the chunk end read row m_begin): no branch around them
-      // keeps the wait before their use exact.
+      // keeps the wait before their use exact.  E' comes in the MFMA result layout (lane
+      // (r, g) = (lane & 15, lane >> 4): row r, columns 4g .. 4g+3); the ciphertext words in
+      // the transposed one that the epilogue stores and compares in (lane 4r + g).
       uint32_t epre[RG][CG];
       uint2 cpre[RG][CG];
       if constexpr (FAST) {
@@ -1199,23 +1203,27 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
         for (int rg = 0; rg < RG; ++rg) {
           const int row0 = rbase + rg * 16 + (lane & 15);
           const int row = row0 < m_end ? row0 : m_begin;
+          const int rowt0 = rbase + rg * 16 + (lane >> 2);
+          const int rowt = rowt0 < m_end ? rowt0 : m_begin;
 #pragma unroll
           for (int cg = 0; cg < CG; ++cg) {
             const int col0 = nn0 + cg * 16 + 4 * (lane >> 4);
             epre[rg][cg] = *(const uint32_t*)(a.E + (size_t)row * n + col0);
-            if constexpr (CMP)
-              cpre[rg][cg] = *(const uint2*)(a.cmp + (size_t)(row >> 3) * a.cmp_stride + a.out_off +
-                                             2 * ((size_t)(row & 7) * n + col0));
+            if constexpr (CMP) {
+              const int colt = nn0 + cg * 16 + 4 * (lane & 3);
+              cpre[rg][cg] = *(const uint2*)(a.cmp + (size_t)(rowt >> 3) * a.cmp_stride + a.out_off +
+                                             2 * ((size_t)(rowt & 7) * n + colt));
+            }
           }
         }
       }
-      for (int s = 0; s < kst; s += UNR) body(s);
-      // the next block's pointers become current; look one block further ahead
+      for (int s = 0; s + UNR < kst; s += UNR) body(s, std::false_type{});
+      body(kst - UNR, std::true_type{});
 #pragma unroll
       for (int rg = 0; rg < RG; ++rg) xp[rg] = xq[rg];
       {
         const int nb = rb + 2 * STRIP_WAVES;
-        row_ptrs(nb < nrb ? nb : (rb + STRIP_WAVES < nrb ? rb + STRIP_WAVES : rb), xq);
+        row_offs(nb < nrb ? nb : (rb + STRIP_WAVES < nrb ? rb + STRIP_WAVES : rb), xq);
       }
 
       // epilogue: lane holds columns 4*(lane>>4) .. +3 of row (lane & 15) of each 16x16 tile
@@ -1238,10 +1246,18 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) v4[i] = (D[i] + (uint32_t)(int32_t)(int8_t)(e4 >> (8 * i))) & qmask;
             const uint2 packed = make_uint2(v4[0] | (v4[1] << 16), v4[2] | (v4[3] << 16));
+            // Lane (r, g) holds columns 4g .. 4g+3 of tile row r.  Transpose the 16 x 4 lane
+            // grid so that lane 4r + g holds them: four consecutive lanes then cover one row's
+            // 32 contiguous bytes, and a store or load touches 16 segments instead of 64.
+            const int src = (((lane & 3) << 4) | (lane >> 2)) << 2;
+            const uint2 sw = make_uint2((uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)packed.x),
+                                        (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)packed.y));
+            const int row2 = rbase + rg * 16 + (lane >> 2), col2 = nn0 + cg * 16 + 4 * (lane & 3);
             if constexpr (CMP) {
-              mism |= rvalid ? (cpre[rg][cg].x ^ packed.x) | (cpre[rg][cg].y ^ packed.y) : 0u;
-            } else if (rvalid) {
-              *(uint2*)(a.out + (size_t)inst * a.out_stride + a.out_off + 2 * ((size_t)r * n + col0)) = packed;
+              mism |= row2 < m_end ? (cpre[rg][cg].x ^ sw.x) | (cpre[rg][cg].y ^ sw.y) : 0u;
+            } else if (row2 < m_end) {
+              *(uint2*)(a.out + (size_t)(row2 >> 3) * a.out_stride + a.out_off +
+                        2 * ((size_t)(row2 & 7) * n + col2)) = sw;
             }
           } else {
             if (!rvalid) continue;
@@ -1294,13 +1310,15 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
           }
         }
         if (CMP && a.n_kc == 1) {
-          // rows 0-7 of the tile (lanes with (lane & 15) < 8) are one instance, rows 8-15 the next
+          // Rows 0-7 of the tile are one instance, rows 8-15 the next: the lanes with
+          // (lane & 15) < 8 and the others in the result layout, lanes 0-31 and 32-63 in the
+          // transposed one (fast path).
           const uint64_t bal = __ballot(mism != 0);
+          const uint64_t lo = FAST ? 0x00000000FFFFFFFFull : 0x00FF00FF00FF00FFull;
           const int row_base = rbase + rg * 16;
-          if (lane == 0 && row_base < a.M)
-            atomicOr(&a.flags[row_base >> 3], (uint32_t)((bal & 0x00FF00FF00FF00FFull) != 0));
+          if (lane == 0 && row_base < a.M) atomicOr(&a.flags[row_base >> 3], (uint32_t)((bal & lo) != 0));
           if (lane == 8 && row_base + 8 < a.M)
-            atomicOr(&a.flags[(row_base >> 3) + 1], (uint32_t)((bal & 0xFF00FF00FF00FF00ull) != 0));
+            atomicOr(&a.flags[(row_base >> 3) + 1], (uint32_t)((bal & ~lo) != 0));
         }
       }
     }
