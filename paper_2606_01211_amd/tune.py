@@ -2,11 +2,14 @@
 
 For one lattice dimension and batch size it sweeps the strip width (16-column groups per
 workgroup), the rows per wave iteration and the number of row chunks sharing one
-regenerated strip of A, times the product kernel with the library's own HIP events, checks
-that every shape produces byte-identical ciphertexts (tile shapes must not change the
-arithmetic), and records the fastest shape in a JSON table:
+regenerated strip of A.  For every shape it times, with the library's own HIP events, both
+launches of the product that one KEM step makes: the encryption of a batched encapsulation
+and the re-encryption and compare of the batched decapsulation.  It checks that every shape
+produces byte-identical ciphertexts and shared secrets (tile shapes must not change the
+arithmetic), and records the shape with the smallest sum of the two in a JSON table:
 
-    {"<n>": {"col_groups": cg, "row_groups": rg, "m_chunks": mc, "us": t, "batch": b}, ...}
+    {"<n>": {"col_groups": cg, "row_groups": rg, "m_chunks": mc, "us": t_enc + t_cmp,
+             "us_encrypt": t_enc, "us_compare": t_cmp, "batch": b}, ...}
 
 Contexts created by the binding load the table next to this file (tuning.json) when it
 exists.
@@ -68,47 +71,60 @@ def tune(n: int, batch: int, reps: int = 3, verbose: bool = True) -> dict:
     p = lwe.params(pid)
     dev = torch.device("cuda:0")
     ctx = lwe.Context(0)
+    # one stream: the compare launch is timed without the decapsulation's concurrent hash
+    ctx.set_side_stream(False)
     g = lwe_inputs.rng(3, 77)
-    pk = np.concatenate([lwe_inputs.random_bytes(g, 1, 16)[0],
-                         (lwe_inputs.random_bytes(g, 1, 16 * n).view("<u2") & (2 ** p.logq - 1)).view(np.uint8)[0]])
-    d_pk = torch.from_numpy(pk.copy()).to(dev)
-    d_coins = torch.from_numpy(lwe_inputs.coins(g, batch)).to(dev)
+    pk = np.zeros(p.pk_bytes, np.uint8)
+    sk = np.zeros(p.sk_bytes, np.uint8)
+    ctx.keygen_batch(pid, 1, lwe_inputs.random_bytes(g, 1, 16), lwe_inputs.random_bytes(g, 1, 16),
+                     lwe_inputs.random_bytes(g, 1, 32), pk, sk)
+    d_pk = torch.from_numpy(pk).to(dev)
+    d_sk = torch.from_numpy(sk).to(dev)
     d_mu = torch.from_numpy(lwe_inputs.messages(g, batch, p.mu_bytes)).to(dev)
     d_ct = torch.empty((batch, p.ct_bytes), dtype=torch.uint8, device=dev)
+    d_ss = torch.empty((batch, 32), dtype=torch.uint8, device=dev)
+    d_ss2 = torch.empty_like(d_ss)
+
+    def timed(name, fn):
+        fn()  # warm-up / buffer growth
+        torch.cuda.synchronize()
+        ctx.prof_reset()
+        ctx.prof_enable(True)
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        prof = ctx.prof_read()
+        ctx.prof_enable(False)
+        launches, ms = prof.get(name, (0, 0.0))
+        return 1e3 * ms / launches if launches else None
+
     results = []
-    ref_digest = None
+    ref = None
     for cg, rg in SHAPES:
         if not lds_fits(cg, n):
             continue
         for mc in M_CHUNKS:
             ctx.set_tuning(pid, col_groups=cg, row_groups=rg, m_chunks=mc)
-            ctx.test_encrypt(pid, batch, d_pk, d_coins, d_mu, d_ct)  # warm-up / buffer growth
-            torch.cuda.synchronize()
-            ctx.prof_reset()
-            ctx.prof_enable(True)
-            for _ in range(reps):
-                ctx.test_encrypt(pid, batch, d_pk, d_coins, d_mu, d_ct)
-            torch.cuda.synchronize()
-            prof = ctx.prof_read()
-            ctx.prof_enable(False)
-            launches, ms = prof.get("prod_strip", (0, 0.0))
-            if not launches:
+            us_enc = timed("prod_strip", lambda: ctx.encaps_batch(pid, batch, d_pk, d_mu, d_ct, d_ss))
+            us_cmp = timed("prod_strip_cmp", lambda: ctx.decaps_batch(pid, batch, d_sk, d_ct, d_ss2))
+            if us_enc is None or us_cmp is None:
                 continue
-            us = 1e3 * ms / launches
-            digest = hashlib.sha256(d_ct.cpu().numpy().tobytes()).hexdigest()
-            if ref_digest is None:
-                ref_digest = digest
-            same = digest == ref_digest
-            results.append({"col_groups": cg, "row_groups": rg, "m_chunks": mc, "us": us, "identical": same})
+            digest = hashlib.sha256(d_ct.cpu().numpy().tobytes() + d_ss.cpu().numpy().tobytes()).hexdigest()
+            if ref is None:
+                ref = digest
+            same = digest == ref and bool(torch.equal(d_ss, d_ss2))
+            results.append({"col_groups": cg, "row_groups": rg, "m_chunks": mc, "us": us_enc + us_cmp,
+                            "us_encrypt": us_enc, "us_compare": us_cmp, "identical": same})
             if verbose:
-                print("cg=%d rg=%d mc=%2d  %8.1f us  %s" % (cg, rg, mc, us, "ok" if same else "DIFFERENT"),
-                      flush=True)
+                print("cg=%d rg=%d mc=%2d  encrypt %8.1f us  compare %8.1f us  %s"
+                      % (cg, rg, mc, us_enc, us_cmp, "ok" if same else "DIFFERENT"), flush=True)
             if not same:
-                raise RuntimeError("tile shape cg=%d rg=%d mc=%d changed the ciphertexts" % (cg, rg, mc))
+                raise RuntimeError("tile shape cg=%d rg=%d mc=%d changed the results" % (cg, rg, mc))
     ctx.close()
     best = min(results, key=lambda r: r["us"])
     return {"col_groups": best["col_groups"], "row_groups": best["row_groups"], "m_chunks": best["m_chunks"],
-            "us": best["us"], "batch": batch, "sweep": results}
+            "us": best["us"], "us_encrypt": best["us_encrypt"], "us_compare": best["us_compare"],
+            "batch": batch, "sweep": results}
 
 
 def main(argv=None) -> int:
