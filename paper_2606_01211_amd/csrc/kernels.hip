@@ -700,10 +700,9 @@ __device__ __forceinline__ uint32_t epi_store(const ProdArgs& a, int row, int co
 __device__ __forceinline__ void flag_tile(const ProdArgs& a, int row_base, uint32_t mism) {
   const uint64_t bal = __ballot(mism != 0);
   const int lane = threadIdx.x & 63;
-  if (lane == 0 && row_base < a.M)
-    atomicOr(&a.flags[row_base >> 3], (uint32_t)((bal & 0xffffffffull) != 0));
-  if (lane == 32 && row_base + 8 < a.M)
-    atomicOr(&a.flags[(row_base >> 3) + 1], (uint32_t)((bal >> 32) != 0));
+  // OR-ing a zero changes nothing: only a mismatch issues an atomic
+  if (lane == 0 && row_base < a.M && (bal & 0xffffffffull)) atomicOr(&a.flags[row_base >> 3], 1u);
+  if (lane == 32 && row_base + 8 < a.M && (bal >> 32)) atomicOr(&a.flags[(row_base >> 3) + 1], 1u);
 }
 
 // ---- the paper's sets (prime q) ----
@@ -1316,9 +1315,11 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
           const uint64_t bal = __ballot(mism != 0);
           const uint64_t lo = FAST ? 0x00000000FFFFFFFFull : 0x00FF00FF00FF00FFull;
           const int row_base = rbase + rg * 16;
-          if (lane == 0 && row_base < a.M) atomicOr(&a.flags[row_base >> 3], (uint32_t)((bal & lo) != 0));
-          if (lane == 8 && row_base + 8 < a.M)
-            atomicOr(&a.flags[(row_base >> 3) + 1], (uint32_t)((bal & ~lo) != 0));
+          // Only a mismatch issues an atomic (OR-ing a zero changes nothing).  An atomic
+          // in every block would hold the next block's first wait on the X loads for its
+          // round trip, vector memory operations completing in order.
+          if (lane == 0 && row_base < a.M && (bal & lo)) atomicOr(&a.flags[row_base >> 3], 1u);
+          if (lane == 8 && row_base + 8 < a.M && (bal & ~lo)) atomicOr(&a.flags[(row_base >> 3) + 1], 1u);
         }
       }
     }
@@ -1352,9 +1353,8 @@ __global__ void k_finalize(ProdArgs a) {
     const uint64_t b1 = __ballot(mism != 0 && inst != inst0);
     int inst_last = inst;
     for (int off = 32; off > 0; off >>= 1) inst_last = max(inst_last, __shfl_xor(inst_last, off));
-    if (lane == 0 && inst0 >= 0) atomicOr(&a.flags[inst0], (uint32_t)(b0 != 0));
-    if (lane == 0 && inst_last != inst0 && inst_last >= 0)
-      atomicOr(&a.flags[inst_last], (uint32_t)(b1 != 0));
+    if (lane == 0 && inst0 >= 0 && b0) atomicOr(&a.flags[inst0], 1u);
+    if (lane == 0 && inst_last != inst0 && inst_last >= 0 && b1) atomicOr(&a.flags[inst_last], 1u);
   }
 }
 
