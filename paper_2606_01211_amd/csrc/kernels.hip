@@ -243,110 +243,6 @@ __device__ __forceinline__ void aes_ctr_block_rep_fixed(const uint32_t* __restri
 }
 
 // ======================================================================================
-// AES with 32 lane-indexed copies of T0 only (32 KB, conflict-free lookups), for kernels that
-// cannot spare the 64 KB of the T0/T2 copies above: word e*32 + c holds T0[e] for copy
-// c = lane & 31.  A lookup address takes an extract and a shift-or (the 128-byte stride is
-// not a byte move); T1..T3 are rotations of T0:
-//   t_j = T0[s_j.b0] ^ rotl16(T0[s_j+2.b2]) ^ rotl8(T0[s_j+1.b1] ^ rotl16(T0[s_j+3.b3]) ^ rotr8(rk)).
-// ======================================================================================
-constexpr int TQ_WORDS = 256 * 32;
-
-__device__ __forceinline__ void load_tables_q(uint32_t* TQ, const uint32_t* __restrict__ T0) {
-  for (int i = threadIdx.x; i < TQ_WORDS; i += blockDim.x) TQ[i] = T0[i >> 5];
-}
-
-template <int BYTE>
-__device__ __forceinline__ uint32_t q_look(const uint32_t* __restrict__ TQ, uint32_t x, uint32_t off) {
-  return *(const uint32_t*)((const char*)TQ + ((((x >> (8 * BYTE)) & 0xffu) << 7) | off));
-}
-
-// One CTR keystream block (same definition as aes_ctr_block); off = (lane & 31) * 4, rkr as
-// for aes_ctr_block_rep.
-template <class RK>
-__device__ __forceinline__ void aes_ctr_block_q(const uint32_t* __restrict__ TQ, uint32_t off, const RK& rk,
-                                                const uint32_t* rkr, uint32_t dom_le, uint64_t b, uint32_t o[4]) {
-  uint32_t s[4];
-  s[0] = dom_le ^ rk[0];
-  s[1] = rk[1];
-  s[2] = bswap32((uint32_t)(b >> 32)) ^ rk[2];
-  s[3] = bswap32((uint32_t)b) ^ rk[3];
-#pragma unroll
-  for (int r = 1; r < 10; ++r) {
-    uint32_t t[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const uint32_t a0 = q_look<0>(TQ, s[j], off);
-      const uint32_t a1 = q_look<1>(TQ, s[(j + 1) & 3], off);
-      const uint32_t a2 = q_look<2>(TQ, s[(j + 2) & 3], off);
-      const uint32_t a3 = q_look<3>(TQ, s[(j + 3) & 3], off);
-      t[j] = x3(a0, rotl32(a2, 16), rotl32(x3(a1, rotl32(a3, 16), rkr[4 * (r - 1) + j]), 8));
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) s[j] = t[j];
-  }
-  // Final round: S(x) is byte 2 of T0[x].
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const uint32_t a0 = q_look<0>(TQ, s[j], off);
-    const uint32_t a1 = q_look<1>(TQ, s[(j + 1) & 3], off);
-    const uint32_t a2 = q_look<2>(TQ, s[(j + 2) & 3], off);
-    const uint32_t a3 = q_look<3>(TQ, s[(j + 3) & 3], off);
-    const uint32_t lo = __builtin_amdgcn_perm(a1, a0, 0x0c0c0602u);
-    const uint32_t hi = __builtin_amdgcn_perm(a3, a2, 0x06020c0cu);
-    o[j] = x3(lo, hi, rk[40 + j]);
-  }
-}
-
-// The fixed-round-1 form (see aes_round1_fixed_rep) for the T0-only tables.
-template <class RK>
-__device__ __forceinline__ void aes_round1_fixed_q(const uint32_t* __restrict__ TQ, uint32_t off, const RK& rk,
-                                                   const uint32_t* rkr, uint32_t dom_le, uint32_t fx[6]) {
-  const uint32_t s0 = dom_le ^ rk[0], s1 = rk[1], s2 = rk[2];
-  fx[0] = q_look<0>(TQ, s0, off) ^ rotl32(q_look<2>(TQ, s2, off), 16);
-  fx[1] = q_look<1>(TQ, s1, off) ^ rkr[0];
-  fx[2] = q_look<0>(TQ, s1, off) ^ rotl32(x3(q_look<1>(TQ, s2, off), rotl32(q_look<3>(TQ, s0, off), 16), rkr[1]), 8);
-  fx[3] = q_look<0>(TQ, s2, off) ^ rotl32(q_look<2>(TQ, s0, off), 16);
-  fx[4] = rotl32(q_look<3>(TQ, s1, off), 16) ^ rkr[2];
-  fx[5] = rotl32(q_look<2>(TQ, s1, off), 16) ^ rotl32(x3(q_look<1>(TQ, s0, off), rotl32(q_look<3>(TQ, s2, off), 16), rkr[3]), 8);
-}
-
-template <class RK>
-__device__ __forceinline__ void aes_ctr_block_q_fixed(const uint32_t* __restrict__ TQ, uint32_t off, const RK& rk,
-                                                      const uint32_t* rkr, const uint32_t fx[6], uint32_t b_lo,
-                                                      uint32_t o[4]) {
-  const uint32_t s3 = bswap32(b_lo) ^ rk[3];
-  uint32_t s[4];
-  s[0] = fx[0] ^ rotl32(fx[1] ^ rotl32(q_look<3>(TQ, s3, off), 16), 8);
-  s[1] = fx[2] ^ rotl32(q_look<2>(TQ, s3, off), 16);
-  s[2] = fx[3] ^ rotl32(fx[4] ^ q_look<1>(TQ, s3, off), 8);
-  s[3] = fx[5] ^ q_look<0>(TQ, s3, off);
-#pragma unroll
-  for (int r = 2; r < 10; ++r) {
-    uint32_t t[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const uint32_t a0 = q_look<0>(TQ, s[j], off);
-      const uint32_t a1 = q_look<1>(TQ, s[(j + 1) & 3], off);
-      const uint32_t a2 = q_look<2>(TQ, s[(j + 2) & 3], off);
-      const uint32_t a3 = q_look<3>(TQ, s[(j + 3) & 3], off);
-      t[j] = x3(a0, rotl32(a2, 16), rotl32(x3(a1, rotl32(a3, 16), rkr[4 * (r - 1) + j]), 8));
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) s[j] = t[j];
-  }
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const uint32_t a0 = q_look<0>(TQ, s[j], off);
-    const uint32_t a1 = q_look<1>(TQ, s[(j + 1) & 3], off);
-    const uint32_t a2 = q_look<2>(TQ, s[(j + 2) & 3], off);
-    const uint32_t a3 = q_look<3>(TQ, s[(j + 3) & 3], off);
-    const uint32_t lo = __builtin_amdgcn_perm(a1, a0, 0x0c0c0602u);
-    const uint32_t hi = __builtin_amdgcn_perm(a3, a2, 0x06020c0cu);
-    o[j] = x3(lo, hi, rk[40 + j]);
-  }
-}
-
-// ======================================================================================
 // Limb split: a 16-bit value x (already reduced mod q) equals lo + 256 hi (mod 2^16) with
 // lo = sext8(x & 0xff) and hi = sext8(((x + 0x80) >> 8) & 0xff).  The int8 byte of lo is the
 // low byte of x itself.
@@ -973,10 +869,10 @@ __global__ void __launch_bounds__(1024) k_prod_stream(ProdArgs a, int ks_per_wav
 // columns) into LDS once, already split into limbs and laid out as MFMA fragments, and
 // then streams every row tile of its row chunk through it.  The MFMA computes the
 // transposed tile (A strip as the first operand), so each lane ends up holding four
-// consecutive columns of one output row: the epilogue reads E' four bytes and writes the
-// result eight bytes at a time.
-//   LDS: the strip, [ksteps][CG][limb][64 lanes][16 bytes] (dynamic), beside the AES tables
-//   (static: 32 KB conflict-free or 4 KB, see TAB below).
+// consecutive columns of one output row: the epilogue reads E' four bytes, and stores or
+// compares the result eight bytes at a time after a lane transpose.
+//   LDS: the strip, [ksteps][CG][limb][64 lanes][16 bytes] (dynamic), and the AES table
+//   copies (64 KB, beside it or inside its space during the regeneration, see TAB below).
 // Workgroup ids are remapped so that each XCD (ids congruent mod 8) processes a
 // contiguous range of tiles, i.e. the same row chunks share that XCD's L2.
 // ======================================================================================
@@ -985,10 +881,12 @@ constexpr int STRIP_WAVES = 8;
 // UNR: contraction steps per unrolled loop body, and the depth of the X register ring (X
 // fragments are requested UNR - 1 steps ahead; the strip is padded to a multiple of UNR).
 // TAB: where the strip comes from.  0: the expanded copy a.Amat (unfused variant; the loop
-// and epilogue are the same); 1: AES with the 4 KB tables; 2: AES with the 32 KB
-// conflict-free tables; 3: AES with the sampler's 64 KB conflict-free tables (one address
-// per byte move, one rotation per column; about half of TAB 2's instructions per block).
-// The launch takes the largest tables that fit beside the strip.
+// and epilogue are the same).  3 and 4: AES with the 64 KB conflict-free T0/T2 copies (one
+// address per byte move, one rotation per column), 3 with the copies in static LDS beside the
+// strip, 4 (strips of 64 KB or more, where the two do not fit together) with the copies in
+// the first 64 KB of the strip's own space: the blocks that land elsewhere are written first;
+// those of the first 64 KB are held in registers (eight per thread) until every lookup is
+// done, then written over the copies.
 template <int CG, int RG, bool CMP, int UNR, int TAB>
 __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
   constexpr bool MAT = TAB == 0;
@@ -996,8 +894,11 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
   constexpr int YD = (UNR * CG) % 3 == 0 ? 3 : 2;
   static_assert((UNR * CG) % YD == 0, "strip fragment ring does not tile the loop body");
   // static: a compile-time address for the table lookups
-  __shared__ uint32_t T[TAB == 3 ? TR_WORDS : (TAB == 2 ? TQ_WORDS : (TAB == 1 ? 1024 : 1))];
+  static_assert(TAB == 0 || TAB == 3 || TAB == 4, "strip table mode");
+  __shared__ uint32_t T[TAB == 3 ? TR_WORDS : 1];
   extern __shared__ uint32_t smem[];
+  // the T0/T2 copies: static (TAB 3) or in the strip's space (TAB 4)
+  uint32_t* const TRt = TAB == 4 ? smem : T;
   uint8_t* strip = (uint8_t*)smem;
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int total = a.n_jt * a.n_kc * a.n_mt;
@@ -1023,14 +924,11 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
   for (int i = 0; i < 36; ++i) rkr[i] = rotl32(rk[4 + i], 24);
   const uint32_t qoff = (uint32_t)(lane & 31) << 2;
 
-  if constexpr (TAB == 1) load_tables(T, a.T0);
-  if constexpr (TAB == 2) load_tables_q(T, a.T0);
-  if constexpr (TAB == 3) load_tables_rep(T, a.T0);
+  if constexpr (!MAT) load_tables_rep(TRt, a.T0);
   __syncthreads();
   // domain 0 and block indices below 2^32 (n <= 32768): round 1's fixed part once per workgroup
   uint32_t fx[6];
-  if constexpr (TAB == 2) aes_round1_fixed_q(T, qoff, rk, rkr, 0u, fx);
-  if constexpr (TAB == 3) aes_round1_fixed_rep(T, qoff, qoff + 128, rk, rkr, 0u, fx);
+  if constexpr (!MAT) aes_round1_fixed_rep(TRt, qoff, qoff + 128, rk, rkr, 0u, fx);
 
   // ---- regenerate (or, unfused, copy) the strip ----
   // Item t = one AES block = 8 consecutive contraction rows of one column.  Items are
@@ -1068,34 +966,50 @@ __global__ void __launch_bounds__(64 * STRIP_WAVES) k_prod_strip(ProdArgs a) {
       }
     }
   };
+  auto gen = [&](int t, uint32_t (&w)[4]) __attribute__((always_inline)) {
+    const Item it = item(t);
+    const int c = nn0 + it.col_local, k = k0 + 8 * it.kb;
+    if constexpr (MAT) {
+      // entries outside A read a valid one; fixup overwrites them below
+      const int cc = c < n ? c : 0, kk = k < k0 + k_len ? k : k0;
+      const uint4 v = *(const uint4*)(a.Amat + (size_t)cc * n + kk);
+      w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+    } else {
+      aes_ctr_block_rep_fixed(TRt, qoff, qoff + 128, rk, rkr, fx, (uint32_t)(((uint64_t)c * n + k) >> 3), w);
+    }
+  };
+  // TAB 4: items below HELD land in the table copies' 64 KB (128 items per 2 KB fragment pair)
+  constexpr int HELD = TAB == 4 ? TR_WORDS * 4 / 2048 * 128 : 0;
   constexpr int ILP = 4;
-  for (int t0 = threadIdx.x; t0 < items; t0 += ILP * blockDim.x) {
+  for (int t0 = HELD + threadIdx.x; t0 < items; t0 += ILP * blockDim.x) {
     int tt[ILP];
     uint32_t w[ILP][4];
 #pragma unroll
     for (int j = 0; j < ILP; ++j) {
       const int t = t0 + j * blockDim.x;
       tt[j] = t < items ? t : t0;  // past the end: recompute t0, stored once
-      const Item it = item(tt[j]);
-      const int c = nn0 + it.col_local, k = k0 + 8 * it.kb;
-      if constexpr (MAT) {
-        // entries outside A read a valid one; fixup overwrites them below
-        const int cc = c < n ? c : 0, kk = k < k0 + k_len ? k : k0;
-        const uint4 v = *(const uint4*)(a.Amat + (size_t)cc * n + kk);
-        w[j][0] = v.x; w[j][1] = v.y; w[j][2] = v.z; w[j][3] = v.w;
-      } else if constexpr (TAB == 1) {
-        aes_ctr_block(T, rk, 0u, ((uint64_t)c * n + k) >> 3, w[j]);
-      } else if constexpr (TAB == 2) {
-        aes_ctr_block_q_fixed(T, qoff, rk, rkr, fx, (uint32_t)(((uint64_t)c * n + k) >> 3), w[j]);
-      } else {
-        aes_ctr_block_rep_fixed(T, qoff, qoff + 128, rk, rkr, fx, (uint32_t)(((uint64_t)c * n + k) >> 3), w[j]);
-      }
+      gen(tt[j], w[j]);
     }
 #pragma unroll
     for (int j = 0; j < ILP; ++j) {
       fixup(item(tt[j]), w[j]);
       if (j == 0 || tt[j] != t0) put(tt[j], w[j]);
     }
+  }
+  if constexpr (TAB == 4) {
+    // the launch guarantees items >= HELD (a strip of at least 64 KB)
+    constexpr int PER = HELD / (64 * STRIP_WAVES);
+    static_assert(HELD % (64 * STRIP_WAVES) == 0, "held items per thread");
+    uint32_t wh[PER][4];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int t = threadIdx.x + j * 64 * STRIP_WAVES;
+      gen(t, wh[j]);
+      fixup(item(t), wh[j]);
+    }
+    __syncthreads();  // every lookup into the copies is done
+#pragma unroll
+    for (int j = 0; j < PER; ++j) put(threadIdx.x + j * 64 * STRIP_WAVES, wh[j]);
   }
   __syncthreads();
 
@@ -1983,18 +1897,16 @@ int product_strip_unroll(int, int, int) { return 3; }
 
 template <int CG, int RG, int UNR>
 static hipError_t launch_strip_t(const ProdArgs& a, hipStream_t s) {
-  const size_t lds = product_strip_lds_bytes(CG, a.kc_len, UNR) - 4096;  // the T-tables are static
-  // the largest conflict-free tables that fit beside the strip, else the 4 KB ones
-  const int tab = a.Amat ? 0
-                : lds + TR_WORDS * 4 <= 160 * 1024 ? 3
-                : lds + TQ_WORDS * 4 <= 160 * 1024 ? 2
-                                                   : 1;
+  const size_t lds = product_strip_lds_bytes(CG, a.kc_len, UNR) - 4096;  // the strip alone
+  // the table copies beside the strip when both fit, else inside the strip's space (which is
+  // then at least 96 KB, more than the copies' 64 KB)
+  const int tab = a.Amat ? 0 : lds + TR_WORDS * 4 <= 160 * 1024 ? 3 : 4;
+  if (tab == 4 && lds < TR_WORDS * 4) return hipErrorInvalidValue;
   // compare mode reads the received ciphertexts instead of writing them
   const bool cmp = a.mode == PM_COMPARE;
   auto kern = tab == 0 ? (cmp ? k_prod_strip<CG, RG, true, UNR, 0> : k_prod_strip<CG, RG, false, UNR, 0>)
-            : tab == 1 ? (cmp ? k_prod_strip<CG, RG, true, UNR, 1> : k_prod_strip<CG, RG, false, UNR, 1>)
-            : tab == 2 ? (cmp ? k_prod_strip<CG, RG, true, UNR, 2> : k_prod_strip<CG, RG, false, UNR, 2>)
-                       : (cmp ? k_prod_strip<CG, RG, true, UNR, 3> : k_prod_strip<CG, RG, false, UNR, 3>);
+            : tab == 3 ? (cmp ? k_prod_strip<CG, RG, true, UNR, 3> : k_prod_strip<CG, RG, false, UNR, 3>)
+                       : (cmp ? k_prod_strip<CG, RG, true, UNR, 4> : k_prod_strip<CG, RG, false, UNR, 4>);
   const int total = a.n_jt * a.n_kc * a.n_mt;
   const unsigned grid = (unsigned)(8 * ((total + 7) / 8));
   hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * STRIP_WAVES), lds, s, a);
@@ -2085,16 +1997,14 @@ hipError_t launch_final_ss(int count, const uint32_t* flags, const uint8_t* kpri
 
 template <int CG, int RG, int UNR>
 static hipError_t allow_lds_strip_u() {
-  const void* kerns[8] = {(const void*)k_prod_strip<CG, RG, false, UNR, 0>,
+  const void* kerns[6] = {(const void*)k_prod_strip<CG, RG, false, UNR, 0>,
                           (const void*)k_prod_strip<CG, RG, true, UNR, 0>,
-                          (const void*)k_prod_strip<CG, RG, false, UNR, 1>,
-                          (const void*)k_prod_strip<CG, RG, true, UNR, 1>,
-                          (const void*)k_prod_strip<CG, RG, false, UNR, 2>,
-                          (const void*)k_prod_strip<CG, RG, true, UNR, 2>,
                           (const void*)k_prod_strip<CG, RG, false, UNR, 3>,
-                          (const void*)k_prod_strip<CG, RG, true, UNR, 3>};
-  for (int i = 0; i < 8; ++i) {
-    const int dyn = 160 * 1024 - (i >= 6 ? TR_WORDS * 4 : (i >= 4 ? TQ_WORDS * 4 : 4096));
+                          (const void*)k_prod_strip<CG, RG, true, UNR, 3>,
+                          (const void*)k_prod_strip<CG, RG, false, UNR, 4>,
+                          (const void*)k_prod_strip<CG, RG, true, UNR, 4>};
+  for (int i = 0; i < 6; ++i) {
+    const int dyn = 160 * 1024 - (i == 2 || i == 3 ? TR_WORDS * 4 : 0);
     hipError_t e = hipFuncSetAttribute(kerns[i], hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     if (e != hipSuccess) return e;
   }
