@@ -62,6 +62,11 @@ SAMPLE_LDS_PER_BLOCK = 148
 # 12-round permutation body (1317 instructions each) plus the block's load and bit
 # interleaving; SQ_INSTS_VALU gives 475 K per wave for 160 blocks
 HASH_VALU_PER_BLOCK = 2960
+# Per absorbed block, per wave of the one-record-per-thread SHA3 kernel (k_hash_records_one):
+# the 24-round permutation on the whole state of one record per lane (4343 instructions in
+# the compiled loop: 2880 v_bitop3, 1392 v_alignbit, the rest XOR) plus the block's 34-word
+# absorb and state moves
+HASH_ONE_VALU_PER_BLOCK = 4420
 # LDS: 256 CUs x 128 bytes per clock x 2.4 GHz
 PEAK_LDS_TBS = 256 * 128 * 2.4e9 / 1e12
 
@@ -111,8 +116,10 @@ def parse():
     ap.add_argument("--lane-side-stream", action="store_true",
                     help="let the lanes' decapsulations hash on their context's second stream too "
                          "(two streams per lane)")
-    ap.add_argument("--lane-hash-lanes", type=int, default=2, choices=(1, 2),
-                    help="lanes per record of the SHA3 kernels of every lane and of the serial run")
+    ap.add_argument("--lane-hash-lanes", type=int, default=1, choices=(1, 2),
+                    help="lanes per record of the SHA3 kernels of every lane and of the serial run: "
+                         "1 (k_hash_records_one, fewer instructions per record, the better pipelined "
+                         "rate) or 2 (k_hash_records, half the chain length per launch)")
     ap.add_argument("--eager", action="store_true",
                     help="feed the pipelined lanes call by call instead of replaying each lane's step as "
                          "a captured HIP graph")
@@ -646,16 +653,18 @@ def main():
             "valu_instr_per_block": SAMPLE_VALU_PER_BLOCK, "lds_lookups_per_block": SAMPLE_LDS_PER_BLOCK,
             "valu_bound_us_per_step": 1e6 * valu_s, "lds_bound_us_per_step": 1e6 * lds_s,
             "measured_us_per_step": 1e6 * t_s, "frac": max(valu_s, lds_s) / t_s}
-    if "hash_records" in rooflines and args.lane_hash_lanes == 2:
-        # Each record pair of lanes is one dependent chain of ct_perms absorbed blocks; a wave
-        # issues at most one VALU instruction per 4 cycles.  The chain's issue bound per launch
-        # is ct_perms x instructions per block x 4 cycles at the 2.4 GHz clock.
+    if "hash_records" in rooflines:
+        # Each record (one lane, or a pair of lanes) is one dependent chain of ct_perms absorbed
+        # blocks; a wave issues at most one VALU instruction per 4 cycles.  The chain's issue
+        # bound per launch is ct_perms x instructions per block x 4 cycles at the 2.4 GHz clock.
+        per_block = HASH_VALU_PER_BLOCK if args.lane_hash_lanes == 2 else HASH_ONE_VALU_PER_BLOCK
         t_h = kern["hash_records"]["avg_us"] * 1e-6
-        chain_s = ct_perms * HASH_VALU_PER_BLOCK * 4 / 2.4e9
+        chain_s = ct_perms * per_block * 4 / 2.4e9
         rooflines["hash_records"]["issue_bound"] = {
-            "valu_instr_per_block_per_wave": HASH_VALU_PER_BLOCK, "blocks_per_record": ct_perms,
-            "waves_per_launch": 2 * B // 64, "chain_bound_us": 1e6 * chain_s, "measured_us": 1e6 * t_h,
-            "frac": chain_s / t_h}
+            "kernel": "k_hash_records" if args.lane_hash_lanes == 2 else "k_hash_records_one",
+            "valu_instr_per_block_per_wave": per_block, "blocks_per_record": ct_perms,
+            "waves_per_launch": args.lane_hash_lanes * B // 64, "chain_bound_us": 1e6 * chain_s,
+            "measured_us": 1e6 * t_h, "frac": chain_s / t_h}
     if "prod_strip" in rooflines:
         mch = ctx.get_tuning(pid)["m_chunks"] or 8
         fused = not args.unfused
