@@ -541,11 +541,12 @@ def test_strip_split_k_8192(ctx, orc):
         assert ct[i].tobytes() == Bp.astype("<u2").tobytes() + V.astype("<u2").tobytes(), i
 
 
-def test_strip_small_tables_4096(ctx, orc):
-    """40 encapsulations at n = 4096 (a key size of the serving mix): the strip there is too
-    tall for the 32 KB conflict-free AES tables beside it, so the strip kernel regenerates A
-    with the 4 KB tables.  Encryption and the decapsulation's compare mode against the oracle,
-    one ciphertext tampered."""
+def test_strip_tables_in_strip_4096(ctx, orc):
+    """40 encapsulations at n = 4096 (a key size of the serving mix): the 128 KB strip leaves no
+    room for the 64 KB AES table copies beside it, so the strip kernel keeps them in the first
+    64 KB of the strip's own space while it regenerates A (the blocks that land there held in
+    registers until the lookups are done).  Encryption and the decapsulation's compare mode
+    against the oracle, one ciphertext tampered."""
     lp, op = _pair(orc, 4096)
     g = lwe_inputs.rng(0, 4096 + 40)
     pk, sk = _keypair(orc, op, g)
@@ -553,7 +554,7 @@ def test_strip_small_tables_4096(ctx, orc):
     mus = lwe_inputs.messages(g, count, op.mu_bytes)
     ct = np.zeros((count, op.ct_bytes), np.uint8)
     ss = np.zeros((count, 32), np.uint8)
-    say("strip 4 KB tables 4096 encaps", count)
+    say("strip tables in strip 4096 encaps", count)
     ctx.encaps_batch(lp.pid, count, pk, mus, ct, ss)
     for i in (0, count - 1):
         oct_, oss = orc.kem_encaps(op, pk, mus[i].tobytes())
@@ -561,10 +562,57 @@ def test_strip_small_tables_4096(ctx, orc):
     bad = ct.copy()
     bad[7, 16 * 4096 + 5] ^= 0x10  # a V coefficient of instance 7
     ss2 = np.zeros((count, 32), np.uint8)
-    say("strip 4 KB tables 4096 decaps", count)
+    say("strip tables in strip 4096 decaps", count)
     ctx.decaps_batch(lp.pid, count, sk, bad, ss2)
     for i in range(count):
         if i != 7:
             assert ss2[i].tobytes() == ss[i].tobytes(), i
     oss, ok = orc.kem_decaps(op, sk, bad[7].tobytes())
     assert not ok and ss2[7].tobytes() == oss
+
+
+@pytest.mark.parametrize("n", [640, 1344])
+def test_strip_tile_shapes(ctx, orc, n):
+    """Every (column groups, row groups) tile the library builds for the strip product, at two
+    row-chunk counts, gives the ciphertexts and shared secrets of the default tile, which are
+    checked against the oracle (Alg. 2-5), and the decapsulation's compare mode rejects the
+    same tampered ciphertext.  The table copies sit beside the strip (n = 640, and one or two
+    column groups at 1344) or inside it (three column groups at 1344); 40 instances make
+    ragged row blocks and row chunks."""
+    from paper_2606_01211_amd import tune
+
+    lp, op = _pair(orc, n)
+    g = lwe_inputs.rng(0, 7100 + n)
+    pk, sk = _keypair(orc, op, g)
+    count = 40
+    mus = lwe_inputs.messages(g, count, op.mu_bytes)
+    saved = ctx.get_tuning(lp.pid)
+    ct0 = np.zeros((count, op.ct_bytes), np.uint8)
+    ss0 = np.zeros((count, 32), np.uint8)
+    say("strip shapes: default", n)
+    ctx.encaps_batch(lp.pid, count, pk, mus, ct0, ss0)
+    for i in (0, count - 1):
+        oct_, oss = orc.kem_encaps(op, pk, mus[i].tobytes())
+        assert ct0[i].tobytes() == oct_ and ss0[i].tobytes() == oss, i
+    bad = ct0.copy()
+    bad[5, 2 * n + 3] ^= 0x04  # a B' coefficient of instance 5
+    oss5, ok = orc.kem_decaps(op, sk, bad[5].tobytes())
+    assert not ok
+    try:
+        for cg, rg in tune.SHAPES:
+            if not tune.lds_fits(cg, n):
+                continue
+            for mc in (3, 8):
+                say("strip shapes", n, cg, rg, mc)
+                ctx.set_tuning(lp.pid, col_groups=cg, row_groups=rg, m_chunks=mc)
+                ct = np.zeros_like(ct0)
+                ss = np.zeros_like(ss0)
+                ctx.encaps_batch(lp.pid, count, pk, mus, ct, ss)
+                assert np.array_equal(ct, ct0) and np.array_equal(ss, ss0), (cg, rg, mc)
+                ss2 = np.zeros_like(ss0)
+                ctx.decaps_batch(lp.pid, count, sk, bad, ss2)
+                keep = [i for i in range(count) if i != 5]
+                assert np.array_equal(ss2[keep], ss0[keep]), (cg, rg, mc)
+                assert ss2[5].tobytes() == oss5, (cg, rg, mc)
+    finally:
+        ctx.set_tuning(lp.pid, **saved)
