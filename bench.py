@@ -120,6 +120,9 @@ def parse():
                     help="lanes per record of the SHA3 kernels of every lane and of the serial run: "
                          "1 (k_hash_records_one, fewer instructions per record, the better pipelined "
                          "rate) or 2 (k_hash_records, half the chain length per launch)")
+    ap.add_argument("--feed-threads", action="store_true",
+                    help="feed the replaying lanes from one host thread each instead of issuing every "
+                         "step's replay from one thread in turn")
     ap.add_argument("--eager", action="store_true",
                     help="feed the pipelined lanes call by call instead of replaying each lane's step as "
                          "a captured HIP graph")
@@ -479,7 +482,11 @@ def main():
             except Exception as e:  # surfaced after the join
                 errors.append(e)
 
-        th = [threading.Thread(target=feed, args=(lane,)) for lane in range(lanes)]
+        # Graph replays need only a seed copy and a launch per step: one thread issues them all,
+        # step i on lane i mod lanes, which starts the lanes sooner than threads contending for
+        # the interpreter lock (each lane's steps stay in its stream's order).
+        single = graphs is not None and lanes > 1 and not args.feed_threads
+        th = [] if single else [threading.Thread(target=feed, args=(lane,)) for lane in range(lanes)]
         for t in th:
             t.start()
         torch.cuda.synchronize()
@@ -487,9 +494,16 @@ def main():
         gc.collect()
         gc.disable()
         t0 = time.perf_counter()
-        go.wait()
-        for t in th:
-            t.join()
+        if single:
+            for i in range(K):
+                lane = i % lanes
+                ev[i][0].record(streams[lane])
+                step(first_seed + i, lane)
+                ev[i][1].record(streams[lane])
+        else:
+            go.wait()
+            for t in th:
+                t.join()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         gc.enable()
@@ -736,7 +750,9 @@ def main():
         "hw_queues": int(os.environ["GPU_MAX_HW_QUEUES"]),
         "lane_side_stream": bool(args.lane_side_stream),
         "lane_hash_lanes": int(args.lane_hash_lanes),
-        "lane_feed": "graph replay" if graphs is not None else "library calls",
+        "lane_feed": ("library calls" if graphs is None else
+                      "graph replay, one feeding thread per lane" if args.feed_threads else
+                      "graph replay, issued in turn from one thread"),
         "graph_matches_calls": graph_check,
         "serial": {"value": serial_value, "ms_per_step": 1e3 * wall1 / K, "feed": "library calls",
                    "batch_latency_ms": {"p50": pct(step_ms1, 50), "p99": pct(step_ms1, 99)}},
