@@ -883,8 +883,8 @@ constexpr int STRIP_WAVES = 8;
 // TAB: where the strip comes from.  0: the expanded copy a.Amat (unfused variant; the loop
 // and epilogue are the same).  3 and 4: AES with the 64 KB conflict-free T0/T2 copies (one
 // address per byte move, one rotation per column), 3 with the copies in static LDS beside the
-// strip, 4 (strips of 64 KB or more, where the two do not fit together) with the copies in
-// the first 64 KB of the strip's own space: the blocks that land elsewhere are written first;
+// strip, 4 (strips too large to sit beside the copies, so larger than 96 KB) with the copies
+// in the first 64 KB of the strip's own space: the blocks that land elsewhere are written first;
 // those of the first 64 KB are held in registers (eight per thread) until every lookup is
 // done, then written over the copies.
 template <int CG, int RG, bool CMP, int UNR, int TAB>
