@@ -458,12 +458,14 @@ def main():
     torch.cuda.synchronize()
     print("warmup done", file=sys.stderr, flush=True)
 
+    issue_ms = {}  # host time from the window's start until every step was queued, per lane count
+
     def timed(lanes, first_seed):
-        """K steps spread round-robin over `lanes` streams, each stream fed by its own host
-        thread (the library calls queue their work without waiting for the device and release
-        the interpreter lock).  The feeding threads are started first and released together by
-        a barrier, after the device has drained, so the timed window holds the K steps and
-        nothing else.  Returns wall seconds, per-step device latencies (ms) and the merged
+        """K steps spread round-robin over `lanes` streams.  Graph replays are issued in turn
+        from this thread; library calls (and --feed-threads) come from one host thread per
+        stream (the library calls queue their work without waiting for the device and release
+        the interpreter lock), started first and released together by a barrier.  Either way
+        the window opens after the device has drained, so it holds the K steps and nothing else.  Returns wall seconds, per-step device latencies (ms) and the merged
         kernel profile (library calls only: a graph replay has no per-kernel events)."""
         for c in ctxs:
             c.prof_reset()
@@ -504,8 +506,10 @@ def main():
             go.wait()
             for t in th:
                 t.join()
+        t_issued = time.perf_counter()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        issue_ms[lanes] = 1e3 * (t_issued - t0)
         gc.enable()
         if errors:
             raise errors[0]
@@ -753,6 +757,8 @@ def main():
         "lane_feed": ("library calls" if graphs is None else
                       "graph replay, one feeding thread per lane" if args.feed_threads else
                       "graph replay, issued in turn from one thread"),
+        # host time from the start of the timed window until the last step was queued
+        "lane_feed_ms": issue_ms.get(S if S > 1 else 1),
         "graph_matches_calls": graph_check,
         "serial": {"value": serial_value, "ms_per_step": 1e3 * wall1 / K, "feed": "library calls",
                    "batch_latency_ms": {"p50": pct(step_ms1, 50), "p99": pct(step_ms1, 99)}},
